@@ -1,0 +1,264 @@
+/*
+ * pmc.h -- C ABI of libpmc: Monte Carlo valuation of compiled payoff
+ * expressions on one MI355X (gfx950) GPU.
+ *
+ * The method is that of Annenkov & Elsman, "Certified Compilation of
+ * Financial Contracts" (PPDP'18): contracts are compiled to a payoff
+ * intermediate language (IL, Sec. 3, Fig. 3), and a pricing engine
+ * evaluates the payoff expression on simulated scenarios of the external
+ * environment and aggregates the discounted value (Sec. 3, Sec. 6.2).  The
+ * engine is parameterised by the compiled payoff, so one expression is
+ * loaded once and priced for many template environments, parameters and
+ * models (Sec. 6.2; templates and instruments, Sec. 2).
+ *
+ * Conventions for every entry point:
+ *   - Return value: PMC_OK (0) or a negative pmc_status.  On error nothing
+ *     is written to output arguments and pmc_last_error() describes it.
+ *     No entry point aborts the process.
+ *   - Host pointers are read during the call only (copied); the caller
+ *     keeps ownership.  Device pointers (suffix _dev) are caller-owned
+ *     device memory on the context's device; they must stay valid until
+ *     the call returns (every call synchronises the context's stream before
+ *     it returns).
+ *   - A pmc_ctx is bound to one device and one HIP stream and must not be
+ *     used from two threads at once.  A pmc_payoff is immutable after load
+ *     and may be used with any context on the same device.
+ *
+ * IL text syntax (S-expressions; one form per IL constructor of Fig. 3 and
+ * the Coq ILExpr type of Sec. 5):
+ *   e  ::= (now) | (real F) | (nat N) | (bool true|false) | (t T)
+ *        | (model LABEL Z) | (payoff T P1 P2)
+ *        | (if e e e) | (loopif e e e T)
+ *        | (neg e) | (not e) | (OP e e)
+ *   OP ::= add | sub | mult | div | min | max | lt | leq | eq | and | or
+ *   T  ::= N | (tvar NAME) | (tplus T T)          -- ILTExpr
+ *   Z  ::= T | (int I) | (tplusz Z Z)             -- ILTExprZ
+ * Value types: N (naturals: now, nat, t), R (reals: real, model, payoff and
+ * arithmetic), B (booleans).  add/min/max work on N or R; sub/mult/div on R;
+ * lt/leq on N or R; eq on equal types; and/or/not on B; neg on R.
+ * Semantics (Fig. 3): (t T) is T + t0; (model l Z) is the observable l on
+ * day Z + t0; (payoff T p q) is +d(T + t0) if (p,q) = (from,to), -d(T + t0)
+ * if (p,q) = (to,from), else 0; (loopif c a b n) checks c on days
+ * t0 .. t0+n and gives a on the first day it holds, else b on day t0+n.
+ * Observables: asset labels are simulated prices (day <= 0 is the spot);
+ * parameter labels are constants (e.g. strike, barrier).
+ */
+#ifndef PMC_H_
+#define PMC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pmc_ctx pmc_ctx;
+typedef struct pmc_payoff pmc_payoff;
+
+typedef enum pmc_status {
+  PMC_OK = 0,
+  PMC_E_ARG = -1,          /* bad argument (NULL, out of range, NaN/Inf) */
+  PMC_E_PARSE = -2,        /* IL text does not follow the grammar above */
+  PMC_E_TYPE = -3,         /* ill-typed IL (Thm. 2 needs well-typed IL) */
+  PMC_E_TENV = -4,         /* template variable unbound or negative */
+  PMC_E_HORIZON = -5,      /* a read day beyond PMC_MAX_HORIZON */
+  PMC_E_NOT_PD = -6,       /* correlation matrix not positive definite */
+  PMC_E_UNSUPPORTED = -7,  /* beyond a documented limit below */
+  PMC_E_HIP = -8,          /* HIP runtime error */
+  PMC_E_OOM = -9           /* device or host allocation failed */
+} pmc_status;
+
+#define PMC_MAX_ASSETS 4
+#define PMC_MAX_HORIZON 65536
+#define PMC_MAX_LOOP_DEPTH 8
+#define PMC_MAX_REGS 24
+
+enum { PMC_RNG_PHILOX = 0, PMC_RNG_SOBOL = 1 };
+enum { PMC_FP32 = 0, PMC_FP64 = 1 };
+enum { PMC_MODE_AUTO = 0, PMC_MODE_TWO_PHASE = 1, PMC_MODE_FUSED = 2 };
+
+/* Library version string (static storage). */
+const char* pmc_version(void);
+
+/* Create a context on HIP device `device` using HIP stream `hip_stream`
+ * (a hipStream_t; NULL means the null stream).  *out receives the handle. */
+int pmc_ctx_create(int device, void* hip_stream, pmc_ctx** out);
+void pmc_ctx_destroy(pmc_ctx* ctx);
+/* Text of the last error on this context (owned by ctx; valid until the
+ * next call on it); with ctx == NULL, the last error of a context-free call
+ * on this thread.  Never NULL. */
+const char* pmc_last_error(const pmc_ctx* ctx);
+
+/* Load a compiled payoff expression (Sec. 3 IL; the engine "compiles once
+ * per instrument", Sec. 6.2).  ctx may be NULL (loading needs no device).
+ * il_text need not be NUL-terminated (len
+ * bytes).  asset_labels[n_assets] name the simulated observables in model
+ * order (1 <= n_assets <= PMC_MAX_ASSETS); param_labels[n_params] name the
+ * constant parameter observables (strike etc.; the paper keeps non-temporal
+ * parameters as constant observables, Sec. 2 footnote); tvar_names[n_tvars]
+ * fix the order of template variables in every tenv array (Sec. 2,
+ * TEnv : Var -> N).  The text is parsed, type-checked and encoded to
+ * bytecode.  Errors: PMC_E_PARSE, PMC_E_TYPE (also for a model label that is
+ * neither an asset nor a parameter), PMC_E_UNSUPPORTED (expression needs
+ * more than PMC_MAX_REGS registers or PMC_MAX_LOOP_DEPTH nested loopifs). */
+int pmc_payoff_load(pmc_ctx* ctx, const char* il_text, size_t len,
+                    const char* const* asset_labels, int n_assets,
+                    const char* const* param_labels, int n_params,
+                    const char* const* tvar_names, int n_tvars, pmc_payoff** out);
+void pmc_payoff_free(pmc_payoff* p);
+
+typedef struct pmc_payoff_info {
+  int n_instr;      /* bytecode length */
+  int n_regs;       /* registers per lane the interpreter uses */
+  int loop_depth;   /* deepest loopif nesting */
+  int n_time_exprs; /* distinct template expressions (folded per tenv) */
+  int n_parties;    /* distinct party names */
+} pmc_payoff_info;
+int pmc_payoff_get_info(const pmc_payoff* p, pmc_payoff_info* out);
+
+/* Simulated days for one template environment: the sorted distinct days > 0
+ * that the expression can read for an asset (the re-indexed time grid of
+ * the Futhark backend, Sec. 6.2; the horizon bound HOR of Sec. 4).
+ * days_out may be NULL to query *n_slots only; else it must hold
+ * max_days entries.  *horizon receives the largest day read (model or
+ * payoff).  Errors: PMC_E_TENV, PMC_E_HORIZON. */
+int pmc_payoff_grid(const pmc_payoff* p, const int32_t* tenv, int32_t* days_out, int max_days,
+                    int* n_slots, int* horizon);
+
+/* Risk-neutral GBM with constant rate, no dividends.  Prices S_a start at
+ * spot[a]; log-price increments between simulated days are
+ * (rate - vol_a^2/2) dt + vol_a sqrt(dt) w_a, w = L z, L L^T = corr,
+ * dt = (day_s - day_{s-1}) * years_per_day.  Discount
+ * d(day) = exp(-rate * day * years_per_day).  corr is n_assets x n_assets
+ * row-major (NULL = identity). */
+typedef struct pmc_gbm {
+  int n_assets;
+  const double* spot;
+  const double* vol;
+  const double* corr;
+  double rate;
+  double years_per_day;
+} pmc_gbm;
+
+typedef struct pmc_opts {
+  uint64_t n_paths;        /* paths per price, 1 .. 2^32 */
+  int rng;                 /* PMC_RNG_PHILOX or PMC_RNG_SOBOL */
+  uint64_t seed;           /* Philox key = (seed mod 2^32, seed div 2^32) */
+  uint32_t instance;       /* Philox counter word 2 (batched: per instance) */
+  int precision;           /* PMC_FP32 (FP32 paths/payoffs, FP64 sums) or PMC_FP64 */
+  int32_t t_now;           /* value of (now), the current time (Sec. 4.1) */
+  const char* party_from;  /* flows party_from -> party_to count positive */
+  const char* party_to;
+  int mode;                /* PMC_MODE_*: fused (generate paths in registers),
+                              two-phase (store SoA paths, then evaluate), auto */
+  void* payoffs_dev;       /* optional: per-path payoff out, float[N] (FP32) or
+                              double[N] (FP64); NULL to skip */
+  int block;               /* threads per block, 0 = default (256) */
+} pmc_opts;
+
+typedef struct pmc_result {
+  double price;       /* mean discounted payoff */
+  double std_err;     /* sample SD (N-1) / sqrt(N) */
+  double sum, sum_sq; /* FP64 sum and sum of squares over paths */
+  uint64_t n_paths;
+  uint64_t path_dates; /* n_paths * n_slots */
+  int n_slots;
+  int mode_used;
+  double ms;          /* device time of the kernel sequence (HIP events) */
+} pmc_result;
+
+/* Price one instrument: tenv[n_tvars] (naturals), params[n_params].
+ * Random words: Philox word w = slot*A + asset of path p is element w%4 of
+ * the block with counter (p, w/4, instance, 0); Sobol dimension w, point p
+ * (unscrambled, Joe-Kuo, Gray order).  Uniforms: FP64 (x+0.5)2^-32, FP32
+ * (x>>9 + 0.5)2^-23; normals by inverse CDF (AS241).
+ * Errors: PMC_E_ARG, PMC_E_TENV, PMC_E_HORIZON, PMC_E_NOT_PD, PMC_E_HIP,
+ * PMC_E_OOM. */
+int pmc_price(pmc_ctx* ctx, const pmc_payoff* p, const int32_t* tenv, const double* params,
+              const pmc_gbm* model, const pmc_opts* opts, pmc_result* out);
+
+/* Batch of instances of one loaded payoff (templated instruments priced
+ * with different template values and parameters, Sec. 2 and Sec. 6.2),
+ * run as one persistent launch over (instance, path-tile) work items taken
+ * longest-first from an atomic queue, replayed from a captured HIP graph.
+ * tenv: n_inst x n_tvars; params: n_inst x n_params.  If per_instance_model
+ * is nonzero, spot/vol are n_inst x A and corr n_inst x A x A (each factored
+ * on the device); else the shared model's arrays are used.  instance_ids
+ * (optional) give each instance's Philox counter word 2 (default: its
+ * index).  out[n_inst].  The opts.payoffs_dev output is not supported here. */
+typedef struct pmc_batch {
+  int n_inst;
+  const int32_t* tenv;
+  const double* params;
+  int per_instance_model;
+  const double* spot;
+  const double* vol;
+  const double* corr;
+  const uint32_t* instance_ids;
+} pmc_batch;
+int pmc_price_batch(pmc_ctx* ctx, const pmc_payoff* p, const pmc_batch* batch,
+                    const pmc_gbm* model, const pmc_opts* opts, pmc_result* out);
+
+/* Autotune the batched launch (threads per block, paths per thread) for this
+ * payoff and batch by timing graph replays of every candidate; the choice is
+ * kept in the context and, when cache_path is not NULL, appended to that text
+ * file as a line "key block ppt" (key = device, payoff hash, batch shape) and
+ * reused from it on later calls.  *block_out and *ppt_out receive it. */
+int pmc_autotune_batch(pmc_ctx* ctx, const pmc_payoff* p, const pmc_batch* batch,
+                       const pmc_gbm* model, const pmc_opts* opts, const char* cache_path,
+                       int* block_out, int* ppt_out);
+
+/* Parity hooks.  pmc_gen_paths writes the simulated prices S[slot][asset][path]
+ * (float or double by opts.precision) to paths_dev, and optionally the raw
+ * random words [word][path] (uint32) to words_dev and the normals
+ * [word][path] to normals_dev (same float type).  pmc_eval_paths evaluates
+ * the payoff on caller-supplied prices in that layout, writing per-path
+ * payoffs to opts.payoffs_dev (may be NULL) and the sums to *out. */
+int pmc_gen_paths(pmc_ctx* ctx, const pmc_payoff* p, const int32_t* tenv, const pmc_gbm* model,
+                  const pmc_opts* opts, void* paths_dev, uint32_t* words_dev, void* normals_dev);
+int pmc_eval_paths(pmc_ctx* ctx, const pmc_payoff* p, const int32_t* tenv, const double* params,
+                   const pmc_gbm* model, const pmc_opts* opts, const void* paths_dev,
+                   pmc_result* out);
+
+/* Lower Cholesky factors of n row-major m x m matrices, computed on the
+ * device in FP64 (the factor every price call uses).  Host in/out.
+ * Errors: PMC_E_NOT_PD (first failing matrix index in pmc_last_error). */
+int pmc_cholesky(pmc_ctx* ctx, const double* a, int n, int m, double* l_out);
+
+/* ---- learned surrogate: MLP 8 -> W -> W -> W -> 1 (GELU), BF16 weights and
+ * activations with FP32 accumulation on MFMA; FP32 master weights and Adam.
+ * Inputs are min-max scaled to [-1, 1] by the library (lo/hi per input);
+ * the network predicts price / y_scale. */
+typedef struct pmc_mlp pmc_mlp;
+int pmc_mlp_create(pmc_ctx* ctx, int n_in, int width, uint64_t seed, const double* in_lo,
+                   const double* in_hi, double y_scale, pmc_mlp** out);
+void pmc_mlp_free(pmc_mlp* m);
+/* Number of parameters (weights and biases of all layers). */
+int64_t pmc_mlp_num_params(const pmc_mlp* m);
+/* Host FP32 copies of the master weights in the order W1 b1 W2 b2 W3 b3 W4 b4,
+ * each W row-major [out][in]. */
+int pmc_mlp_get_params(const pmc_mlp* m, float* out);
+int pmc_mlp_set_params(pmc_mlp* m, const float* in);
+typedef struct pmc_train_opts {
+  int batch;          /* samples per Adam step */
+  double lr_max, lr_min; /* cosine schedule from lr_max to lr_min over total_steps */
+  int64_t total_steps;
+  double beta1, beta2, eps;
+} pmc_train_opts;
+/* One pass over n samples (x_dev [n][n_in] float, raw inputs; y_dev [n]
+ * float prices) in order; *mean_loss receives the mean squared error of the
+ * scaled target over the pass. */
+int pmc_mlp_train_epoch(pmc_mlp* m, const float* x_dev, const float* y_dev, int64_t n,
+                        const pmc_train_opts* o, double* mean_loss);
+/* Forward pass: y_dev[n] prices (float) for raw inputs x_dev[n][n_in]. */
+int pmc_mlp_infer(pmc_mlp* m, const float* x_dev, float* y_dev, int64_t n);
+/* Loss and gradients of the mean squared error over n samples at the
+ * current weights (FP32 gradients, host out, same order as get_params). */
+int pmc_mlp_loss_grad(pmc_mlp* m, const float* x_dev, const float* y_dev, int64_t n,
+                      double* loss, float* grad_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMC_H_ */

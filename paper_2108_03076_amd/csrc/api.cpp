@@ -1,0 +1,765 @@
+// C-ABI of libpmc (declared in include/pmc.h): contexts, payoff loading,
+// pricing launches (single, batched persistent with graph replay), parity
+// hooks and the batch autotuner.
+#include <hip/hip_runtime.h>
+#include <rocrand/rocrand.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/pmc.h"
+#include "ilc.h"
+#include "kernels.h"
+
+using namespace pmc;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+  hipError_t ensure(size_t n) {
+    if (n <= cap) return hipSuccess;
+    if (p) { (void)hipFree(p); p = nullptr; cap = 0; }
+    size_t want = std::max<size_t>(n, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) cap = want;
+    return e;
+  }
+};
+
+struct HostPinned {
+  void* p = nullptr;
+  size_t cap = 0;
+  ~HostPinned() { if (p) (void)hipHostFree(p); }
+  hipError_t ensure(size_t n) {
+    if (n <= cap) return hipSuccess;
+    if (p) { (void)hipHostFree(p); p = nullptr; cap = 0; }
+    size_t want = std::max<size_t>(n, 4096);
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e == hipSuccess) cap = want;
+    return e;
+  }
+};
+
+// A packed upload: several host arrays placed at aligned offsets of one
+// device blob, copied with a single async H2D transfer.
+struct Pack {
+  std::vector<uint8_t> bytes;
+  size_t add(const void* src, size_t n) {
+    size_t off = (bytes.size() + 255) & ~size_t(255);
+    bytes.resize(off + n);
+    if (n) std::memcpy(bytes.data() + off, src, n);
+    return off;
+  }
+};
+
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  std::string key;
+  ~GraphCache() { if (exec) (void)hipGraphExecDestroy(exec); }
+};
+
+}  // namespace
+
+struct pmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  DevBuf blob, partial, result, bad, queue, paths, sobol, chol;
+  HostPinned staging;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int sobol_dims = 0;
+  int n_cu = 0;
+  std::string device_name;
+  GraphCache graph;
+  std::map<std::string, std::pair<int, int>> tuned;  // batch shape -> (block, ppt)
+};
+
+struct pmc_payoff {
+  Program prog;
+  uint64_t hash = 0;
+};
+
+// Errors of calls made without a context (payoff loading may run before
+// any device is opened) are kept per thread.
+static thread_local std::string g_err;
+
+static int fail(pmc_ctx* c, int st, const std::string& m) {
+  if (c) c->err = m;
+  else g_err = m;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                           \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? PMC_E_OOM : PMC_E_HIP,            \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                \
+  } while (0)
+
+extern "C" const char* pmc_version(void) { return "pmc 1.0 (gfx950)"; }
+
+extern "C" int pmc_ctx_create(int device, void* stream, pmc_ctx** out) {
+  if (!out) return PMC_E_ARG;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return PMC_E_HIP;
+  auto c = std::make_unique<pmc_ctx>();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  if (hipSetDevice(device) != hipSuccess) return PMC_E_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return PMC_E_HIP;
+  c->n_cu = prop.multiProcessorCount;
+  c->device_name = prop.gcnArchName;
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) return PMC_E_HIP;
+  *out = c.release();
+  return PMC_OK;
+}
+
+extern "C" void pmc_ctx_destroy(pmc_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+extern "C" const char* pmc_last_error(const pmc_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+static std::vector<std::string> names(const char* const* a, int n) {
+  std::vector<std::string> v;
+  for (int i = 0; i < n; ++i) v.emplace_back(a[i] ? a[i] : "");
+  return v;
+}
+
+extern "C" int pmc_payoff_load(pmc_ctx* c, const char* text, size_t len, const char* const* assets,
+                               int n_assets, const char* const* params, int n_params,
+                               const char* const* tvars, int n_tvars, pmc_payoff** out) {
+  if (!out || (!text && len)) return fail(c, PMC_E_ARG, "null argument");
+  if (n_assets < 1 || n_assets > PMC_MAX_ASSETS) return fail(c, PMC_E_UNSUPPORTED, "1..4 assets supported");
+  if (n_params < 0 || n_tvars < 0 || (n_params && !params) || (n_tvars && !tvars) || !assets)
+    return fail(c, PMC_E_ARG, "bad label arrays");
+  auto p = std::make_unique<pmc_payoff>();
+  std::string err;
+  int st = compile(text, len, names(assets, n_assets), names(params, n_params), names(tvars, n_tvars), p->prog, err);
+  if (st != PMC_OK) return fail(c, st, err);
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < len; ++i) h = (h ^ (uint8_t)text[i]) * 1099511628211ull;
+  p->hash = h;
+  *out = p.release();
+  return PMC_OK;
+}
+
+extern "C" void pmc_payoff_free(pmc_payoff* p) { delete p; }
+
+extern "C" int pmc_payoff_get_info(const pmc_payoff* p, pmc_payoff_info* o) {
+  if (!p || !o) return PMC_E_ARG;
+  o->n_instr = (int)p->prog.code.size();
+  o->n_regs = p->prog.n_regs;
+  o->loop_depth = p->prog.loop_depth;
+  o->n_time_exprs = (int)p->prog.tt.size();
+  o->n_parties = (int)p->prog.parties.size();
+  return PMC_OK;
+}
+
+extern "C" int pmc_payoff_grid(const pmc_payoff* p, const int32_t* tenv, int32_t* days, int max_days,
+                               int* n_slots, int* horizon) {
+  if (!p || (!tenv && !p->prog.tvars.empty()) || !n_slots) return PMC_E_ARG;
+  Grid g;
+  std::string err;
+  int st = plan(p->prog, tenv, g, err);
+  if (st != PMC_OK) return st;
+  *n_slots = (int)g.days.size();
+  if (horizon) *horizon = g.horizon;
+  if (days) {
+    if (max_days < (int)g.days.size()) return PMC_E_ARG;
+    std::copy(g.days.begin(), g.days.end(), days);
+  }
+  return PMC_OK;
+}
+
+extern "C" int pmc_cholesky(pmc_ctx* c, const double* a, int n, int m, double* l) {
+  if (!c || !a || !l || n < 1 || m < 1 || m > 16) return fail(c, PMC_E_ARG, "bad cholesky arguments");
+  HIP_TRY(c, hipSetDevice(c->device));
+  size_t bytes = (size_t)n * m * m * sizeof(double);
+  HIP_TRY(c, c->blob.ensure(bytes));
+  HIP_TRY(c, c->chol.ensure(bytes));
+  HIP_TRY(c, c->bad.ensure(sizeof(int)));
+  const int big = 0x7fffffff;
+  HIP_TRY(c, hipMemcpyAsync(c->bad.p, &big, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->blob.p, a, bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_cholesky((const double*)c->blob.p, (double*)c->chol.p, (int*)c->bad.p, n, m, c->stream));
+  int bad = 0;
+  HIP_TRY(c, hipMemcpyAsync(&bad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(l, c->chol.p, bytes, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (bad != big) return fail(c, PMC_E_NOT_PD, "matrix " + std::to_string(bad) + " is not positive definite");
+  return PMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+namespace {
+
+bool finite(double x) { return std::isfinite(x); }
+
+struct InstanceIn {
+  const int32_t* tenv;
+  const double* params;
+  const double* spot;
+  const double* vol;
+  const double* corr;  // may be null (identity)
+  uint32_t instance;
+};
+
+int check_model(pmc_ctx* c, const Program& P, const pmc_gbm* m) {
+  if (!m) return fail(c, PMC_E_ARG, "null model");
+  if (m->n_assets != (int)P.assets.size()) return fail(c, PMC_E_ARG, "model asset count differs from the payoff's");
+  if (!finite(m->rate) || !finite(m->years_per_day) || m->years_per_day <= 0)
+    return fail(c, PMC_E_ARG, "rate and years_per_day must be finite, years_per_day > 0");
+  return PMC_OK;
+}
+
+int check_instance(pmc_ctx* c, const Program& P, const InstanceIn& in) {
+  const int A = (int)P.assets.size();
+  if (!in.spot || !in.vol) return fail(c, PMC_E_ARG, "null spot or vol");
+  for (int a = 0; a < A; ++a) {
+    if (!finite(in.spot[a]) || in.spot[a] <= 0) return fail(c, PMC_E_ARG, "spot must be finite and > 0");
+    if (!finite(in.vol[a]) || in.vol[a] < 0) return fail(c, PMC_E_ARG, "vol must be finite and >= 0");
+  }
+  if (in.corr)
+    for (int i = 0; i < A * A; ++i)
+      if (!finite(in.corr[i])) return fail(c, PMC_E_ARG, "correlation must be finite");
+  if (!P.params.empty() && !in.params) return fail(c, PMC_E_ARG, "null params");
+  for (size_t q = 0; q < P.params.size(); ++q)
+    if (!finite(in.params[q])) return fail(c, PMC_E_ARG, "parameter '" + P.params[q] + "' is not finite");
+  if (!P.tvars.empty() && !in.tenv) return fail(c, PMC_E_ARG, "null tenv");
+  return PMC_OK;
+}
+
+int check_opts(pmc_ctx* c, const pmc_opts* o) {
+  if (!o) return fail(c, PMC_E_ARG, "null opts");
+  if (o->n_paths < 1 || o->n_paths > (1ull << 32)) return fail(c, PMC_E_ARG, "n_paths must be in 1..2^32");
+  if (o->rng != PMC_RNG_PHILOX && o->rng != PMC_RNG_SOBOL) return fail(c, PMC_E_ARG, "bad rng");
+  if (o->precision != PMC_FP32 && o->precision != PMC_FP64) return fail(c, PMC_E_ARG, "bad precision");
+  if (!o->party_from || !o->party_to) return fail(c, PMC_E_ARG, "null party name");
+  if (o->block != 0 && (o->block % 64 != 0 || o->block > 256 || o->block < 64))
+    return fail(c, PMC_E_ARG, "block must be 64, 128, 192 or 256");
+  if (o->mode < 0 || o->mode > 2) return fail(c, PMC_E_ARG, "bad mode");
+  return PMC_OK;
+}
+
+// Host-side tables of one launch (all instances), before upload.
+template <typename T>
+struct Tables {
+  std::vector<int32_t> itab;
+  std::vector<T> rtab;
+  std::vector<double> corr;  // Cholesky inputs, A x A per instance
+  std::vector<InstDesc> desc;
+  int max_dims = 0;          // largest slots * assets
+  int64_t path_dates = 0;
+  std::vector<int> n_slots;
+};
+
+template <typename T>
+int build_instance(pmc_ctx* c, const Program& P, const pmc_gbm& m, const pmc_opts& o,
+                   const InstanceIn& in, int idx, Tables<T>& tb) {
+  Grid g;
+  std::string err;
+  int st = plan(P, in.tenv, g, err);
+  if (st != PMC_OK) return fail(c, st, err);
+  const int A = (int)P.assets.size();
+  InstDesc d{};
+  d.tt_off = (int32_t)tb.itab.size();
+  tb.itab.insert(tb.itab.end(), g.tt.begin(), g.tt.end());
+  d.sign_off = (int32_t)tb.itab.size();
+  for (auto& pr : P.pairs) {
+    const std::string& f = P.parties[pr.first];
+    const std::string& t = P.parties[pr.second];
+    int s = 0;
+    if (f == o.party_from && t == o.party_to) s = 1;
+    else if (f == o.party_to && t == o.party_from) s = -1;
+    tb.itab.push_back(s);
+  }
+  d.daymap_off = (int32_t)tb.itab.size();
+  tb.itab.insert(tb.itab.end(), g.daymap.begin(), g.daymap.end());
+  d.horizon = g.horizon;
+  d.n_slots = (int32_t)g.days.size();
+  d.t_now = o.t_now;
+  // d(day) = exp(-r * day * years_per_day)
+  d.disc_off = (int32_t)tb.rtab.size();
+  for (int32_t day = 0; day <= g.horizon; ++day) tb.rtab.push_back((T)std::exp(-m.rate * (double)day * m.years_per_day));
+  // per slot: dt, sqrt(dt) with dt = (day_s - day_{s-1}) * years_per_day
+  d.slot_off = (int32_t)tb.rtab.size();
+  int32_t prev = 0;
+  for (int32_t day : g.days) {
+    const double dt = (double)(day - prev) * m.years_per_day;
+    tb.rtab.push_back((T)dt);
+    tb.rtab.push_back((T)std::sqrt(dt));
+    prev = day;
+  }
+  d.param_off = (int32_t)tb.rtab.size();
+  for (size_t q = 0; q < P.params.size(); ++q) tb.rtab.push_back((T)in.params[q]);
+  d.model_off = (int32_t)tb.rtab.size();
+  for (int a = 0; a < A; ++a) tb.rtab.push_back((T)(m.rate - 0.5 * in.vol[a] * in.vol[a]));
+  for (int a = 0; a < A; ++a) tb.rtab.push_back((T)in.vol[a]);
+  for (int a = 0; a < A; ++a) tb.rtab.push_back((T)in.spot[a]);
+  d.chol_off = (int32_t)tb.corr.size();
+  for (int i = 0; i < A; ++i)
+    for (int j = 0; j < A; ++j) tb.corr.push_back(in.corr ? in.corr[i * A + j] : (i == j ? 1.0 : 0.0));
+  d.instance = in.instance;
+  d.n_paths = (uint32_t)std::min<uint64_t>(o.n_paths, 0xFFFFFFFFull);
+  if (o.n_paths == (1ull << 32)) return fail(c, PMC_E_UNSUPPORTED, "n_paths = 2^32 is not supported per instance");
+  tb.max_dims = std::max(tb.max_dims, (int)g.days.size() * A);
+  tb.path_dates += (int64_t)o.n_paths * (int64_t)g.days.size();
+  tb.n_slots.push_back((int)g.days.size());
+  tb.desc.push_back(d);
+  (void)idx;
+  return PMC_OK;
+}
+
+int ensure_sobol(pmc_ctx* c, int dims) {
+  if (dims <= c->sobol_dims) return PMC_OK;
+  if (dims > 20000) return fail(c, PMC_E_UNSUPPORTED, "Sobol needs more than 20000 dimensions");
+  const unsigned int* v = nullptr;
+  if (rocrand_get_direction_vectors32(&v, ROCRAND_DIRECTION_VECTORS_32_JOEKUO6) != ROCRAND_STATUS_SUCCESS || !v)
+    return fail(c, PMC_E_HIP, "Sobol direction numbers unavailable");
+  const int want = std::max(dims, 64);
+  HIP_TRY(c, c->sobol.ensure((size_t)want * 32 * sizeof(uint32_t)));
+  HIP_TRY(c, hipMemcpyAsync(c->sobol.p, v, (size_t)want * 32 * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->sobol_dims = want;
+  return PMC_OK;
+}
+
+int sobol_bits(uint64_t n) {
+  int b = 1;
+  while (b < 32 && ((n - 1) >> b) != 0) ++b;
+  return b;
+}
+
+// Uploads the tables and fills the launch arguments (except work items).
+template <typename T>
+int upload(pmc_ctx* c, const Program& P, const Tables<T>& tb, const pmc_opts& o, McLaunch& L,
+           const std::vector<int2>* work) {
+  Pack pk;
+  std::vector<T> consts(P.consts.size());
+  for (size_t i = 0; i < consts.size(); ++i) consts[i] = (T)P.consts[i];
+  const size_t o_code = pk.add(P.code.data(), P.code.size() * sizeof(Instr));
+  const size_t o_consts = pk.add(consts.data(), consts.size() * sizeof(T));
+  const size_t o_desc = pk.add(tb.desc.data(), tb.desc.size() * sizeof(InstDesc));
+  const size_t o_itab = pk.add(tb.itab.data(), tb.itab.size() * sizeof(int32_t));
+  const size_t o_rtab = pk.add(tb.rtab.data(), tb.rtab.size() * sizeof(T));
+  const size_t o_corr = pk.add(tb.corr.data(), tb.corr.size() * sizeof(double));
+  size_t o_work = 0;
+  if (work) o_work = pk.add(work->data(), work->size() * sizeof(int2));
+  HIP_TRY(c, c->blob.ensure(pk.bytes.size()));
+  HIP_TRY(c, c->staging.ensure(pk.bytes.size()));
+  // the previous launch may still read the staging buffer's last copy
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::memcpy(c->staging.p, pk.bytes.data(), pk.bytes.size());
+  HIP_TRY(c, hipMemcpyAsync(c->blob.p, c->staging.p, pk.bytes.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, c->chol.ensure(std::max<size_t>(tb.corr.size(), 1) * sizeof(double)));
+  uint8_t* b = (uint8_t*)c->blob.p;
+  L = McLaunch{};
+  L.code = (const Instr*)(b + o_code);
+  L.consts = b + o_consts;
+  L.desc = (const InstDesc*)(b + o_desc);
+  L.itab = (const int32_t*)(b + o_itab);
+  L.rtab = b + o_rtab;
+  L.chol = (const double*)c->chol.p;
+  L.work = work ? (const int2*)(b + o_work) : nullptr;
+  L.k0 = (uint32_t)(o.seed & 0xFFFFFFFFull);
+  L.k1 = (uint32_t)(o.seed >> 32);
+  L.n_assets = (int)P.assets.size();
+  L.ppt = 1;
+  if (o.rng == PMC_RNG_SOBOL) {
+    int st = ensure_sobol(c, tb.max_dims);
+    if (st != PMC_OK) return st;
+    L.sobol = (const uint32_t*)c->sobol.p;
+    L.sobol_bits = sobol_bits(o.n_paths);
+  }
+  L.chol_in = (const double*)(b + o_corr);
+  return PMC_OK;
+}
+
+int factor(pmc_ctx* c, const McLaunch& L, int n_inst, int A) {
+  HIP_TRY(c, c->bad.ensure(sizeof(int)));
+  HIP_TRY(c, launch_fill_u32((uint32_t*)c->bad.p, 0x7fffffffu, 1, c->stream));
+  HIP_TRY(c, launch_cholesky(L.chol_in, (double*)c->chol.p, (int*)c->bad.p, n_inst, A, c->stream));
+  return PMC_OK;
+}
+
+int finish(pmc_ctx* c, int n_inst, const std::vector<uint64_t>& n_paths, const std::vector<int>& n_slots,
+           int mode_used, double ms, pmc_result* out) {
+  std::vector<double2> res(n_inst);
+  int bad = 0;
+  HIP_TRY(c, hipMemcpyAsync(res.data(), c->result.p, n_inst * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&bad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (bad != 0x7fffffff) return fail(c, PMC_E_NOT_PD, "correlation matrix of instance " + std::to_string(bad) + " is not positive definite");
+  for (int i = 0; i < n_inst; ++i) {
+    const double N = (double)n_paths[i];
+    pmc_result r{};
+    r.sum = res[i].x;
+    r.sum_sq = res[i].y;
+    r.n_paths = n_paths[i];
+    r.price = r.sum / N;
+    const double var = N > 1 ? std::max(0.0, (r.sum_sq - r.sum * r.sum / N) / (N - 1.0)) : 0.0;
+    r.std_err = std::sqrt(var / N);
+    r.n_slots = n_slots[i];
+    r.path_dates = n_paths[i] * (uint64_t)n_slots[i];
+    r.mode_used = mode_used;
+    r.ms = ms;
+    out[i] = r;
+  }
+  return PMC_OK;
+}
+
+template <typename T>
+int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double* params, const pmc_gbm* m,
+              const pmc_opts* o, pmc_result* out, const void* given_paths, bool eval_only) {
+  const Program& P = p->prog;
+  InstanceIn in{tenv, params, m->spot, m->vol, m->corr, o->instance};
+  int st = check_instance(c, P, in);
+  if (st != PMC_OK) return st;
+  Tables<T> tb;
+  st = build_instance<T>(c, P, *m, *o, in, 0, tb);
+  if (st != PMC_OK) return st;
+  const int A = (int)P.assets.size();
+  const int block = o->block ? o->block : 256;
+  const uint64_t N = o->n_paths;
+  const int n_slots = tb.desc[0].n_slots;
+  int mode = o->mode;
+  if (eval_only) {
+    mode = PMC_MODE_TWO_PHASE;
+  } else if (mode == PMC_MODE_AUTO) {
+    // fused unless the window would regenerate much more than one path
+    Grid g;
+    std::string err;
+    plan(P, tenv, g, err);
+    int64_t cost = fused_generation_cost(P, g, A, 1 << 22);
+    mode = (cost >= 0 && cost <= 2 * (int64_t)std::max(1, n_slots)) ? PMC_MODE_FUSED : PMC_MODE_TWO_PHASE;
+  }
+  const uint32_t tiles = (uint32_t)((N + block - 1) / block);
+  tb.desc[0].n_tiles = tiles;
+  tb.desc[0].first_item = 0;
+  McLaunch L;
+  st = upload<T>(c, P, tb, *o, L, nullptr);
+  if (st != PMC_OK) return st;
+  HIP_TRY(c, c->partial.ensure((size_t)tiles * sizeof(double2)));
+  HIP_TRY(c, c->result.ensure(sizeof(double2)));
+  L.partial = (double2*)c->partial.p;
+  L.n_work = (int)tiles;
+  L.payoff_out = o->payoffs_dev;
+  HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+  st = factor(c, L, 1, A);
+  if (st != PMC_OK) return st;
+  const int prec = sizeof(T) == 8 ? 1 : 0;
+  if (mode == PMC_MODE_TWO_PHASE) {
+    if (given_paths) {
+      L.paths = given_paths;
+    } else {
+      const size_t bytes = (size_t)n_slots * A * N * sizeof(T);
+      HIP_TRY(c, c->paths.ensure(std::max<size_t>(bytes, 4)));
+      HIP_TRY(c, launch_pathgen(prec, o->rng, L, c->paths.p, nullptr, nullptr, (uint32_t)N, 256, c->stream));
+      L.paths = c->paths.p;
+    }
+    if (n_slots == 0) L.paths = nullptr;
+    HIP_TRY(c, launch_mc(prec, o->rng, n_slots > 0, L, (int)tiles, block, c->stream));
+  } else {
+    HIP_TRY(c, launch_mc(prec, o->rng, false, L, (int)tiles, block, c->stream));
+  }
+  HIP_TRY(c, launch_reduce(L.partial, L.desc, 1, (double2*)c->result.p, c->stream));
+  HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(c, hipEventSynchronize(c->ev1));
+  float ms = 0;
+  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  return finish(c, 1, {N}, {n_slots}, mode, ms, out);
+}
+
+}  // namespace
+
+extern "C" int pmc_price(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double* params,
+                         const pmc_gbm* m, const pmc_opts* o, pmc_result* out) {
+  if (!c || !p || !out) return fail(c, PMC_E_ARG, "null argument");
+  int st = check_model(c, p->prog, m);
+  if (st == PMC_OK) st = check_opts(c, o);
+  if (st != PMC_OK) return st;
+  HIP_TRY(c, hipSetDevice(c->device));
+  return o->precision == PMC_FP64 ? price_one<double>(c, p, tenv, params, m, o, out, nullptr, false)
+                                  : price_one<float>(c, p, tenv, params, m, o, out, nullptr, false);
+}
+
+extern "C" int pmc_eval_paths(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double* params,
+                              const pmc_gbm* m, const pmc_opts* o, const void* paths_dev, pmc_result* out) {
+  if (!c || !p || !out || !paths_dev) return fail(c, PMC_E_ARG, "null argument");
+  int st = check_model(c, p->prog, m);
+  if (st == PMC_OK) st = check_opts(c, o);
+  if (st != PMC_OK) return st;
+  HIP_TRY(c, hipSetDevice(c->device));
+  return o->precision == PMC_FP64 ? price_one<double>(c, p, tenv, params, m, o, out, paths_dev, true)
+                                  : price_one<float>(c, p, tenv, params, m, o, out, paths_dev, true);
+}
+
+namespace {
+template <typename T>
+int gen_paths(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const pmc_gbm* m, const pmc_opts* o,
+              void* paths, uint32_t* words, void* normals) {
+  const Program& P = p->prog;
+  static const double zero_params[64] = {0};
+  std::vector<double> params(P.params.size(), 0.0);
+  InstanceIn in{tenv, params.empty() ? zero_params : params.data(), m->spot, m->vol, m->corr, o->instance};
+  int st = check_instance(c, P, in);
+  if (st != PMC_OK) return st;
+  Tables<T> tb;
+  st = build_instance<T>(c, P, *m, *o, in, 0, tb);
+  if (st != PMC_OK) return st;
+  McLaunch L;
+  st = upload<T>(c, P, tb, *o, L, nullptr);
+  if (st != PMC_OK) return st;
+  st = factor(c, L, 1, (int)P.assets.size());
+  if (st != PMC_OK) return st;
+  HIP_TRY(c, launch_pathgen(sizeof(T) == 8 ? 1 : 0, o->rng, L, paths, words, normals, (uint32_t)o->n_paths, 256, c->stream));
+  int bad = 0;
+  HIP_TRY(c, hipMemcpyAsync(&bad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (bad != 0x7fffffff) return fail(c, PMC_E_NOT_PD, "correlation matrix is not positive definite");
+  return PMC_OK;
+}
+}  // namespace
+
+extern "C" int pmc_gen_paths(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const pmc_gbm* m,
+                             const pmc_opts* o, void* paths_dev, uint32_t* words_dev, void* normals_dev) {
+  if (!c || !p || !paths_dev) return fail(c, PMC_E_ARG, "null argument");
+  int st = check_model(c, p->prog, m);
+  if (st == PMC_OK) st = check_opts(c, o);
+  if (st != PMC_OK) return st;
+  HIP_TRY(c, hipSetDevice(c->device));
+  return o->precision == PMC_FP64 ? gen_paths<double>(c, p, tenv, m, o, paths_dev, words_dev, normals_dev)
+                                  : gen_paths<float>(c, p, tenv, m, o, paths_dev, words_dev, normals_dev);
+}
+
+// ------------------------------------------------------------ batched ------
+namespace {
+
+struct BatchPlan {
+  McLaunch L;
+  int grid = 0, block = 256, ppt = 1, n_inst = 0, mode = PMC_MODE_FUSED;
+  std::vector<uint64_t> n_paths;
+  std::vector<int> n_slots;
+  int64_t path_dates = 0;
+};
+
+template <typename T>
+int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc_gbm* m, const pmc_opts* o,
+                  int block, int ppt, BatchPlan& bp) {
+  const Program& P = p->prog;
+  const int A = (int)P.assets.size();
+  const int I = b->n_inst;
+  Tables<T> tb;
+  tb.desc.reserve(I);
+  for (int i = 0; i < I; ++i) {
+    InstanceIn in;
+    in.tenv = b->tenv ? b->tenv + (size_t)i * P.tvars.size() : nullptr;
+    in.params = b->params ? b->params + (size_t)i * P.params.size() : nullptr;
+    if (b->per_instance_model) {
+      in.spot = b->spot + (size_t)i * A;
+      in.vol = b->vol + (size_t)i * A;
+      in.corr = b->corr ? b->corr + (size_t)i * A * A : nullptr;
+    } else {
+      in.spot = m->spot; in.vol = m->vol; in.corr = m->corr;
+    }
+    in.instance = b->instance_ids ? b->instance_ids[i] : (uint32_t)i;
+    int st = check_instance(c, P, in);
+    if (st != PMC_OK) return st;
+    st = build_instance<T>(c, P, *m, *o, in, i, tb);
+    if (st != PMC_OK) return st;
+  }
+  // work items: (instance, tile), instances with the most slots first
+  const uint64_t N = o->n_paths;
+  const uint32_t tile_paths = (uint32_t)block * (uint32_t)ppt;
+  const uint32_t tiles = (uint32_t)((N + tile_paths - 1) / tile_paths);
+  std::vector<int> order(I);
+  for (int i = 0; i < I; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tb.n_slots[x] > tb.n_slots[y]; });
+  std::vector<int2> work;
+  work.reserve((size_t)I * tiles);
+  for (int i : order)
+    for (uint32_t t = 0; t < tiles; ++t) work.push_back(make_int2(i, (int)t));
+  for (int i = 0; i < I; ++i) {
+    tb.desc[i].n_tiles = tiles;
+    tb.desc[i].first_item = (int32_t)((size_t)i * tiles);
+  }
+  McLaunch L;
+  int st = upload<T>(c, P, tb, *o, L, &work);
+  if (st != PMC_OK) return st;
+  HIP_TRY(c, c->partial.ensure(work.size() * sizeof(double2)));
+  HIP_TRY(c, c->result.ensure((size_t)I * sizeof(double2)));
+  HIP_TRY(c, c->queue.ensure(sizeof(uint32_t)));
+  HIP_TRY(c, c->bad.ensure(sizeof(int)));
+  L.partial = (double2*)c->partial.p;
+  L.n_work = (int)work.size();
+  L.queue = (uint32_t*)c->queue.p;
+  L.ppt = ppt;
+  L.payoff_out = nullptr;
+  bp.L = L;
+  const int occ = mc_occupancy(sizeof(T) == 8 ? 1 : 0, o->rng, A, block);
+  bp.grid = std::max(1, std::min<int>((int)work.size(), c->n_cu * occ));
+  bp.block = block; bp.ppt = ppt; bp.n_inst = I;
+  bp.n_paths.assign(I, N);
+  bp.n_slots = tb.n_slots;
+  bp.path_dates = tb.path_dates;
+  return PMC_OK;
+}
+
+// Enqueue the batched sequence: Cholesky factors, queue reset, persistent
+// MC kernel, per-instance reduction.  Captured once into a graph.
+int batch_enqueue(pmc_ctx* c, const BatchPlan& bp, int prec, int rng, int A) {
+  int st = factor(c, bp.L, bp.n_inst, A);
+  if (st != PMC_OK) return st;
+  const McLaunch& L = bp.L;
+  HIP_TRY(c, launch_fill_u32(L.queue, 0u, 1, c->stream));
+  HIP_TRY(c, launch_mc(prec, rng, false, L, bp.grid, bp.block, c->stream));
+  HIP_TRY(c, launch_reduce(L.partial, L.desc, bp.n_inst, (double2*)c->result.p, c->stream));
+  return PMC_OK;
+}
+
+int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_opts* o, float* ms_out) {
+  const int prec = o->precision == PMC_FP64 ? 1 : 0;
+  const int A = (int)p->prog.assets.size();
+  std::ostringstream key;
+  key << p->hash << ':' << bp.n_inst << ':' << bp.grid << ':' << bp.block << ':' << bp.ppt << ':' << bp.L.n_work
+      << ':' << prec << ':' << o->rng << ':' << c->blob.p << ':' << c->partial.p << ':' << c->result.p << ':'
+      << c->chol.p << ':' << c->sobol.p << ':' << (const void*)bp.L.desc << ':' << (const void*)bp.L.work;
+  if (c->graph.key != key.str()) {
+    if (c->graph.exec) { (void)hipGraphExecDestroy(c->graph.exec); c->graph.exec = nullptr; }
+    c->graph.key.clear();
+    hipStream_t cap = c->stream;
+    bool own = false;
+    if (!cap) {  // the null stream cannot be captured: use a private one
+      HIP_TRY(c, hipStreamCreate(&cap));
+      own = true;
+    }
+    hipStream_t saved = c->stream;
+    c->stream = cap;
+    HIP_TRY(c, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    int st = batch_enqueue(c, bp, prec, o->rng, A);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cap, &graph);
+    c->stream = saved;
+    if (st != PMC_OK) { if (graph) (void)hipGraphDestroy(graph); if (own) (void)hipStreamDestroy(cap); return st; }
+    if (e != hipSuccess) { if (own) (void)hipStreamDestroy(cap); return fail(c, PMC_E_HIP, std::string("graph capture: ") + hipGetErrorString(e)); }
+    e = hipGraphInstantiate(&c->graph.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (own) (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return fail(c, PMC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    c->graph.key = key.str();
+  }
+  HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+  HIP_TRY(c, hipGraphLaunch(c->graph.exec, c->stream));
+  HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(c, hipEventSynchronize(c->ev1));
+  HIP_TRY(c, hipEventElapsedTime(ms_out, c->ev0, c->ev1));
+  return PMC_OK;
+}
+
+std::string tune_key(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc_opts* o) {
+  std::ostringstream k;
+  k << c->device_name << '/' << std::hex << p->hash << std::dec << '/' << b->n_inst << '/' << o->n_paths << '/'
+    << o->precision << '/' << o->rng;
+  return k.str();
+}
+
+int check_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc_gbm* m, const pmc_opts* o) {
+  if (!c || !p || !b) return fail(c, PMC_E_ARG, "null argument");
+  if (b->n_inst < 1) return fail(c, PMC_E_ARG, "n_inst must be >= 1");
+  if (b->per_instance_model && (!b->spot || !b->vol)) return fail(c, PMC_E_ARG, "per-instance model needs spot and vol");
+  int st = check_model(c, p->prog, m);
+  if (st == PMC_OK) st = check_opts(c, o);
+  if (st != PMC_OK) return st;
+  if (o->payoffs_dev) return fail(c, PMC_E_UNSUPPORTED, "per-path payoff output is not supported for batches");
+  if ((uint64_t)b->n_inst * ((o->n_paths + 63) / 64) > (1ull << 31)) return fail(c, PMC_E_UNSUPPORTED, "batch too large");
+  return PMC_OK;
+}
+
+}  // namespace
+
+extern "C" int pmc_price_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc_gbm* m,
+                               const pmc_opts* o, pmc_result* out) {
+  int st = check_batch(c, p, b, m, o);
+  if (st != PMC_OK) return st;
+  if (!out) return fail(c, PMC_E_ARG, "null out");
+  HIP_TRY(c, hipSetDevice(c->device));
+  int block = o->block ? o->block : 256, ppt = 1;
+  auto it = c->tuned.find(tune_key(c, p, b, o));
+  if (it != c->tuned.end() && !o->block) { block = it->second.first; ppt = it->second.second; }
+  BatchPlan bp;
+  st = o->precision == PMC_FP64 ? batch_prepare<double>(c, p, b, m, o, block, ppt, bp)
+                                : batch_prepare<float>(c, p, b, m, o, block, ppt, bp);
+  if (st != PMC_OK) return st;
+  float ms = 0;
+  st = batch_run(c, p, bp, o, &ms);
+  if (st != PMC_OK) return st;
+  return finish(c, bp.n_inst, bp.n_paths, bp.n_slots, PMC_MODE_FUSED, ms, out);
+}
+
+extern "C" int pmc_autotune_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc_gbm* m,
+                                  const pmc_opts* o, const char* cache_path, int* block_out, int* ppt_out) {
+  int st = check_batch(c, p, b, m, o);
+  if (st != PMC_OK) return st;
+  HIP_TRY(c, hipSetDevice(c->device));
+  const std::string key = tune_key(c, p, b, o);
+  if (cache_path) {  // cache file: one "key block ppt" line per entry
+    std::ifstream f(cache_path);
+    std::string k;
+    int bl, pp;
+    while (f >> k >> bl >> pp)
+      if (k == key) {
+        c->tuned[key] = {bl, pp};
+        if (block_out) *block_out = bl;
+        if (ppt_out) *ppt_out = pp;
+        return PMC_OK;
+      }
+  }
+  const int blocks[] = {64, 128, 256};
+  const int ppts[] = {1, 2, 4};
+  float best = 1e30f;
+  int bb = 256, bpp = 1;
+  for (int bl : blocks)
+    for (int pp : ppts) {
+      BatchPlan bp;
+      st = o->precision == PMC_FP64 ? batch_prepare<double>(c, p, b, m, o, bl, pp, bp)
+                                    : batch_prepare<float>(c, p, b, m, o, bl, pp, bp);
+      if (st != PMC_OK) return st;
+      float t = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        float ms = 0;
+        st = batch_run(c, p, bp, o, &ms);
+        if (st != PMC_OK) return st;
+        if (rep > 0) t = std::min(t, ms);   // first replay includes instantiation effects
+      }
+      if (t < best) { best = t; bb = bl; bpp = pp; }
+    }
+  c->tuned[key] = {bb, bpp};
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    f << key << ' ' << bb << ' ' << bpp << '\n';
+  }
+  if (block_out) *block_out = bb;
+  if (ppt_out) *ppt_out = bpp;
+  return PMC_OK;
+}

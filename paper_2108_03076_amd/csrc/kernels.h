@@ -1,0 +1,44 @@
+// Launch interface between the C-ABI host code and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pmc_device.h"
+
+namespace pmc {
+
+// Arguments of the Monte Carlo kernels, type-erased (reals are float or
+// double according to the precision the launcher is called with).
+struct McLaunch {
+  const Instr* code;
+  const void* consts;         // real[n_consts]
+  const InstDesc* desc;       // per instance
+  const int32_t* itab;        // packed int tables
+  const void* rtab;           // packed real tables
+  const double* chol;         // packed FP64 Cholesky factors
+  const double* chol_in;      // packed FP64 correlation matrices (factored on device)
+  const uint32_t* sobol;      // direction numbers [dim][32]
+  int sobol_bits;             // bits of the largest path index
+  const int2* work;           // (instance, tile) items, or nullptr: item = (0, block)
+  int n_work;
+  uint32_t* queue;            // work counter (persistent launch) or nullptr
+  double2* partial;           // per item: (sum, sum of squares)
+  void* payoff_out;           // optional per-path payoffs of instance 0
+  const void* paths;          // stored prices [slot][asset][path] (two-phase)
+  uint32_t k0, k1;            // Philox key
+  int ppt;                    // paths per thread per item
+  int n_assets;
+};
+
+hipError_t launch_mc(int precision, int rng, bool from_memory, const McLaunch& a, int grid, int block,
+                     hipStream_t s);
+hipError_t launch_pathgen(int precision, int rng, const McLaunch& a, void* paths, uint32_t* words,
+                          void* normals, uint32_t n_paths, int block, hipStream_t s);
+hipError_t launch_reduce(const double2* partial, const InstDesc* desc, int n_inst, double2* out,
+                         hipStream_t s);
+hipError_t launch_cholesky(const double* a, double* l, int* bad, int n, int m, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s);
+// Largest resident blocks per CU for the persistent MC kernel.
+int mc_occupancy(int precision, int rng, int n_assets, int block);
+
+}  // namespace pmc

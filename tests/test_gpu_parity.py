@@ -1,0 +1,286 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded streams.
+
+Bars (FP32 paths): random words bit-exact; normals within 2e-6 (AS241's
+7-digit variant in binary32 against PPND16 in binary64); prices on every
+simulated day within 2e-5 relative (binary32 log-price accumulation over up
+to 1260 steps); per-path payoffs within 1e-5 relative outside the tie-band
+(paths whose oracle payoff jumps when every price moves by 3e-5);
+prices within 0.1 standard errors.  FP64 paths: normals and prices within
+1e-13 relative, prices within 1e-12 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import gpu_payoff, model_kw, opts_kw, oracle_problem, sample_ids, tie_band
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _small(cfg, **over):
+    import dataclasses
+    return dataclasses.replace(cfg, **over)
+
+
+def _gen(cfg, n, tenv=None):
+    import paper_2108_03076_amd as P
+    tenv = cfg.tenv if tenv is None else tenv
+    pay = gpu_payoff(cfg)
+    days, _ = pay.grid(tenv)
+    A = len(cfg.asset_labels)
+    dt = torch.float64 if cfg.precision == "f64" else torch.float32
+    paths = torch.empty(len(days) * A * n, dtype=dt, device="cuda")
+    words = torch.empty(len(days) * A * n, dtype=torch.int32, device="cuda")
+    normals = torch.empty(len(days) * A * n, dtype=dt, device="cuda")
+    P.gen_paths(pay, paths, words, normals, tenv, **model_kw(cfg), **opts_kw(cfg, n))
+    torch.cuda.synchronize()
+    D = len(days)
+    S = paths.double().cpu().numpy().reshape(D, A, n).transpose(2, 0, 1)          # [path][slot][asset]
+    wd = words.cpu().numpy().view(np.uint32).reshape(D * A, n).T                  # [path][word]
+    z = normals.double().cpu().numpy().reshape(D * A, n).T
+    return pay, days, S, wd, z, paths
+
+
+CASES = {
+    "c3_short": _small(W.C3, tenv=[37]),
+    "c2": W.C2,
+    "c1": W.C1,
+    "c2_philox": _small(W.C2, rng="philox"),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_streams_and_paths(name):
+    cfg = CASES[name]
+    n = 1000                                     # ragged: 3 full blocks of 256 and a tail
+    print(f"[parity] streams {name} n={n}", flush=True)
+    pay, days, S, wd, z, _ = _gen(cfg, n)
+    prob = oracle_problem(cfg)
+    assert days == prob.days
+    ids = np.arange(n)
+    ow = prob.words(ids)
+    assert np.array_equal(wd, ow), "random words differ"
+    oz = prob.normals(ids).reshape(n, -1)
+    oS = prob.paths(ids)
+    if cfg.precision == "f64":
+        assert np.max(np.abs(z - oz) / np.maximum(1, np.abs(oz))) < 1e-13
+        assert np.max(np.abs(S / oS - 1)) < 1e-13
+    else:
+        assert np.max(np.abs(z - oz) / np.maximum(1, np.abs(oz))) < 2e-6
+        assert np.max(np.abs(S / oS - 1)) < 2e-5
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_payoffs_on_stored_paths(name):
+    """Payoff arithmetic alone: the GPU evaluates its own stored paths, the
+    oracle evaluates the same values upcast exactly to binary64."""
+    import paper_2108_03076_amd as P
+    cfg = CASES[name]
+    n = 1000
+    print(f"[parity] eval_paths {name}", flush=True)
+    pay, days, S, _, _, paths = _gen(cfg, n)
+    prob = oracle_problem(cfg)
+    dt = torch.float64 if cfg.precision == "f64" else torch.float32
+    out = torch.empty(n, dtype=dt, device="cuda")
+    r = P.eval_paths(pay, paths, cfg.tenv, cfg.params, **model_kw(cfg), **opts_kw(cfg, n, payoffs=out))
+    gpu = out.double().cpu().numpy()
+    ref = prob.payoffs_on_paths(S)
+    tol = 1e-12 if cfg.precision == "f64" else 1e-5
+    band = tie_band(prob, S, 3e-5) if cfg.precision == "f32" else np.zeros(n, bool)
+    bad = (np.abs(gpu - ref) > tol * np.maximum(np.abs(ref), 1.0)) & ~band
+    assert not bad.any(), (np.nonzero(bad)[0][:10], gpu[bad][:5], ref[bad][:5])
+    assert band.sum() <= max(5, 5e-3 * n)
+    assert r["sum"] == pytest.approx(gpu.sum(), rel=1e-12, abs=1e-9)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("mode", ["fused", "two_phase"])
+def test_price_matches_oracle(name, mode):
+    import paper_2108_03076_amd as P
+    cfg = CASES[name]
+    n = 4000 if cfg.precision == "f32" else 1 << 14
+    print(f"[parity] price {name} {mode} n={n}", flush=True)
+    pay = gpu_payoff(cfg)
+    dt = torch.float64 if cfg.precision == "f64" else torch.float32
+    out = torch.empty(n, dtype=dt, device="cuda")
+    r = P.price(pay, cfg.tenv, cfg.params, **model_kw(cfg), **opts_kw(cfg, n, mode=mode, payoffs=out))
+    prob = oracle_problem(cfg)
+    ids = np.arange(n)
+    ref_pay = prob.payoffs(ids)
+    from oracle.mc import estimate
+    ref, se = estimate(ref_pay)
+    gpu = out.double().cpu().numpy()
+    if cfg.precision == "f64":
+        assert r["price"] == pytest.approx(ref, rel=1e-12)
+        assert np.allclose(gpu, ref_pay, rtol=1e-12, atol=1e-12)
+    else:
+        assert abs(r["price"] - ref) <= 0.1 * se, (r["price"], ref, se)
+        S = prob.paths(ids)
+        band = tie_band(prob, S, 3e-5)
+        scale = np.maximum(np.abs(ref_pay), np.max(S, axis=(1, 2)))
+        bad = (np.abs(gpu - ref_pay) > 2e-5 * scale) & ~band
+        assert not bad.any(), (np.nonzero(bad)[0][:10], gpu[bad][:5], ref_pay[bad][:5])
+    assert r["std_err"] == pytest.approx(se, rel=1e-3)
+    assert r["n_slots"] == len(prob.days)
+
+
+def test_c1_full_fp64_matches_oracle_and_black_scholes():
+    import paper_2108_03076_amd as P
+    from oracle import closed_form as cf
+    from oracle.mc import estimate
+    cfg = W.C1
+    print("[parity] C1 full", flush=True)
+    pay = gpu_payoff(cfg)
+    r = P.price(pay, cfg.tenv, cfg.params, **model_kw(cfg), **opts_kw(cfg, cfg.n_paths))
+    ref, se = estimate(oracle_problem(cfg).payoffs(np.arange(cfg.n_paths)))
+    assert r["price"] == pytest.approx(ref, rel=1e-12)
+    bs = cf.bs_call(100, 100, 0.03, 0.2, 1.0)
+    assert abs(r["price"] - bs) < 3 * r["std_err"]
+
+
+def test_c3_full_size_sampled_paths():
+    """2^20 paths x 1260 days in the launch configuration the benchmark times;
+    sampled per-path payoffs against the oracle computed one by one."""
+    import paper_2108_03076_amd as P
+    from oracle import closed_form as cf
+    cfg = W.C3
+    n = cfg.n_paths
+    print("[parity] C3 full size", flush=True)
+    pay = gpu_payoff(cfg)
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    for mode in ("fused", "two_phase"):
+        r = P.price(pay, cfg.tenv, cfg.params, **model_kw(cfg), **opts_kw(cfg, n, mode=mode, payoffs=out))
+        gpu = out.double().cpu().numpy()
+        ids = sample_ids(n, 48)
+        prob = oracle_problem(cfg)
+        ref = prob.payoffs(ids)
+        S = prob.paths(ids)
+        band = tie_band(prob, S, 3e-5)
+        scale = np.maximum(np.abs(ref), np.max(S, axis=(1, 2)))
+        bad = (np.abs(gpu[ids] - ref) > 2e-5 * scale) & ~band
+        assert not bad.any(), (mode, ids[bad])
+        assert r["sum"] == pytest.approx(gpu.sum(), rel=1e-9)
+        bgk = cf.down_and_out_call(100, 100, cf.bgk_barrier(70, 0.3, 1 / 252), 0.03, 0.3, 5.0)
+        assert abs(r["price"] - bgk) < 3 * r["std_err"] + 0.02, (r["price"], bgk, r["std_err"])
+        assert r["path_dates"] == n * 1260
+
+
+def test_c2_full_size_sampled_paths():
+    import paper_2108_03076_amd as P
+    cfg = W.C2
+    n = cfg.n_paths
+    print("[parity] C2 full size", flush=True)
+    pay = gpu_payoff(cfg)
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    r = P.price(pay, cfg.tenv, cfg.params, **model_kw(cfg), **opts_kw(cfg, n, payoffs=out))
+    gpu = out.double().cpu().numpy()
+    ids = sample_ids(n, 200)
+    prob = oracle_problem(cfg)
+    ref = prob.payoffs(ids)
+    S = prob.paths(ids)
+    band = tie_band(prob, S, 3e-5)
+    bad = (np.abs(gpu[ids] - ref) > 2e-5 * np.maximum(np.abs(ref), 100.0)) & ~band
+    assert not bad.any(), ids[bad]
+    assert r["sum"] == pytest.approx(gpu.sum(), rel=1e-9)
+    assert 70 < r["price"] < 95
+
+
+def test_batch_matches_single_and_oracle():
+    import paper_2108_03076_amd as P
+    from oracle.mc import estimate
+    cfg = _small(W.C4)
+    T = np.array([20, 45, 7, 33, 60, 1, 0, 52], dtype=np.int32)
+    K = np.linspace(90, 110, T.size)
+    B = np.linspace(60, 95, T.size)
+    n = 1500
+    print("[parity] batch", flush=True)
+    pay = gpu_payoff(cfg)
+    res = P.price_batch(pay, T.reshape(-1, 1), np.stack([K, B], 1), **model_kw(cfg), **opts_kw(cfg, n))
+    for i in range(T.size):
+        one = P.price(pay, [int(T[i])], [K[i], B[i]], **model_kw(cfg), **opts_kw(cfg, n, instance=i))
+        assert res[i]["price"] == pytest.approx(one["price"], rel=1e-12, abs=1e-12)
+        prob = oracle_problem(cfg, tenv={"T": int(T[i])}, params=[K[i], B[i]], instance=i)
+        ref, se = estimate(prob.payoffs(np.arange(n)))
+        assert abs(res[i]["price"] - ref) <= 0.1 * se + 1e-9, (i, res[i]["price"], ref, se)
+        assert res[i]["n_slots"] == T[i]
+
+
+def test_batch_per_instance_model_and_determinism():
+    import paper_2108_03076_amd as P
+    from oracle.mc import estimate
+    cfg = W.C5
+    pts = W.c5_points(6, seed=7)
+    n = 2000
+    print("[parity] batch per-instance model", flush=True)
+    pay = gpu_payoff(cfg)
+    tenv = (pts[:, 7].astype(np.int32) - 1).reshape(-1, 1)
+    corr = np.stack([np.array(W.corr_equi(3, r)) for r in pts[:, 6]])
+    kw = dict(spot=pts[:, 0:3], vol=pts[:, 3:6], corr=corr, rate=cfg.rate, years_per_day=cfg.years_per_day,
+              per_instance_model=True)
+    a = P.price_batch(pay, tenv, np.zeros((6, 0)), **kw, **opts_kw(cfg, n))
+    b = P.price_batch(pay, tenv, np.zeros((6, 0)), **kw, **opts_kw(cfg, n))
+    for i in range(6):
+        assert a[i]["sum"] == b[i]["sum"] and a[i]["sum_sq"] == b[i]["sum_sq"]
+        prob = oracle_problem(cfg, tenv={"N": int(tenv[i, 0])}, spot=pts[i, 0:3], vol=pts[i, 3:6],
+                              corr=corr[i], instance=i)
+        ref, se = estimate(prob.payoffs(np.arange(n)))
+        assert abs(a[i]["price"] - ref) <= 0.1 * se + 1e-9, (i, a[i]["price"], ref, se)
+
+
+def test_gpu_cholesky_matches_oracle():
+    from gpu_common import ctx
+    from oracle.model import cholesky
+    g = np.random.default_rng(3)
+    mats = []
+    for _ in range(5):
+        a = g.normal(size=(3, 3))
+        mats.append(a @ a.T + 3 * np.eye(3))
+    mats = np.stack(mats)
+    L = ctx().cholesky(mats)
+    for i in range(5):
+        assert np.allclose(L[i], cholesky(mats[i]), rtol=1e-14, atol=1e-14)
+
+
+def test_gpu_error_paths():
+    import paper_2108_03076_amd as P
+    cfg = W.C2
+    pay = gpu_payoff(cfg)
+    with pytest.raises(P.PmcError) as e:
+        P.price(pay, cfg.tenv, [], **model_kw(cfg, corr=W.corr_equi(3, -0.7)), **opts_kw(cfg, 256))
+    assert e.value.name == "E_NOT_PD"
+    with pytest.raises(P.PmcError) as e:
+        P.price(pay, [-1], [], **model_kw(cfg), **opts_kw(cfg, 256))
+    assert e.value.name == "E_TENV"
+    with pytest.raises(P.PmcError) as e:
+        P.price(pay, [70000], [], **model_kw(cfg), **opts_kw(cfg, 256))
+    assert e.value.name == "E_HORIZON"
+    with pytest.raises(P.PmcError) as e:
+        P.price(pay, cfg.tenv, [], **model_kw(cfg, spot=[100, float("nan"), 100]), **opts_kw(cfg, 256))
+    assert e.value.name == "E_ARG"
+    # the context still works after errors
+    r = P.price(pay, cfg.tenv, [], **model_kw(cfg), **opts_kw(cfg, 256))
+    assert math.isfinite(r["price"])
+
+
+def test_edge_cases_single_path_and_no_slots():
+    import paper_2108_03076_amd as P
+    from oracle.mc import estimate
+    cfg = W.C1
+    pay = gpu_payoff(cfg)
+    r = P.price(pay, cfg.tenv, cfg.params, **model_kw(cfg), **opts_kw(cfg, 1))
+    ref, _ = estimate(oracle_problem(cfg).payoffs(np.arange(1)))
+    assert r["price"] == pytest.approx(ref, rel=1e-12)
+    # maturity 0: only the spot is read (no simulated day); the call pays max(S0-K,0)
+    r = P.price(pay, [0], [90.0], **model_kw(cfg), **opts_kw(cfg, 300))
+    assert r["n_slots"] == 0 and r["price"] == pytest.approx(10.0, rel=1e-12)
+    # deterministic expression: cash at day 10
+    cash = P.Payoff(pay.ctx, "(mult (real 2.0) (payoff 10 X Y))", ["S"])
+    r = P.price(cash, [], [], **model_kw(cfg), **opts_kw(cfg, 777))
+    assert r["price"] == pytest.approx(2 * math.exp(-0.03 * 10 / 252), rel=1e-12)
+    r = P.price(cash, [], [], **model_kw(cfg), **opts_kw(cfg, 777, parties=("Y", "X")))
+    assert r["price"] == pytest.approx(-2 * math.exp(-0.03 * 10 / 252), rel=1e-12)
