@@ -72,11 +72,16 @@ typedef enum pmc_status {
 #define PMC_MAX_ASSETS 4
 #define PMC_MAX_HORIZON 65536
 #define PMC_MAX_LOOP_DEPTH 8
-#define PMC_MAX_REGS 24
+#define PMC_MAX_REGS 31
 
 enum { PMC_RNG_PHILOX = 0, PMC_RNG_SOBOL = 1 };
 enum { PMC_FP32 = 0, PMC_FP64 = 1 };
 enum { PMC_MODE_AUTO = 0, PMC_MODE_TWO_PHASE = 1, PMC_MODE_FUSED = 2 };
+/* Payoff engines: the bytecode interpreter (wavefront-uniform program
+ * counter) or the payoff compiled to a device function at run time (hipRTC;
+ * the first price call of a payoff/precision/rng variant compiles it, which
+ * takes seconds; later calls reuse it).  AUTO selects COMPILED. */
+enum { PMC_ENGINE_AUTO = 0, PMC_ENGINE_INTERPRETER = 1, PMC_ENGINE_COMPILED = 2 };
 
 /* Library version string (static storage). */
 const char* pmc_version(void);
@@ -107,6 +112,13 @@ int pmc_payoff_load(pmc_ctx* ctx, const char* il_text, size_t len,
                     const char* const* param_labels, int n_params,
                     const char* const* tvar_names, int n_tvars, pmc_payoff** out);
 void pmc_payoff_free(pmc_payoff* p);
+
+/* Device source of the compiled payoff engine for this payoff: the engine
+ * kernel body plus the payoff expression translated to a HIP device function
+ * (compile with -DPMC_REAL=float|double -DPMC_RNG=0|1 -DPMC_A=<assets>
+ * -DPMC_MEM=0|1).  Copies at most cap bytes (NUL-terminated) to buf and
+ * stores the full length (without NUL) in *len; buf may be NULL to query. */
+int pmc_payoff_source(const pmc_payoff* p, char* buf, size_t cap, size_t* len);
 
 typedef struct pmc_payoff_info {
   int n_instr;      /* bytecode length */
@@ -155,6 +167,7 @@ typedef struct pmc_opts {
   void* payoffs_dev;       /* optional: per-path payoff out, float[N] (FP32) or
                               double[N] (FP64); NULL to skip */
   int block;               /* threads per block, 0 = default (256) */
+  int engine;              /* PMC_ENGINE_*: how the payoff runs on the device */
 } pmc_opts;
 
 typedef struct pmc_result {
@@ -165,7 +178,10 @@ typedef struct pmc_result {
   uint64_t path_dates; /* n_paths * n_slots */
   int n_slots;
   int mode_used;
-  double ms;          /* device time of the kernel sequence (HIP events) */
+  double ms;          /* device time of the whole kernel sequence (HIP events) */
+  double gen_ms;      /* two-phase only: path generation kernel */
+  double eval_ms;     /* the Monte Carlo / payoff kernel */
+  int engine_used;    /* PMC_ENGINE_INTERPRETER or PMC_ENGINE_COMPILED */
 } pmc_result;
 
 /* Price one instrument: tenv[n_tvars] (naturals), params[n_params].

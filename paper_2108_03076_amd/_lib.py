@@ -26,6 +26,7 @@ STATUS = {0: "OK", -1: "E_ARG", -2: "E_PARSE", -3: "E_TYPE", -4: "E_TENV", -5: "
 RNG = {"philox": 0, "sobol": 1}
 PREC = {"f32": 0, "f64": 1}
 MODE = {"auto": 0, "two_phase": 1, "fused": 2}
+ENGINE = {"auto": 0, "interpreter": 1, "compiled": 2}
 
 
 class PmcError(RuntimeError):
@@ -43,13 +44,15 @@ class Gbm(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("n_paths", C.c_uint64), ("rng", C.c_int), ("seed", C.c_uint64), ("instance", C.c_uint32),
                 ("precision", C.c_int), ("t_now", C.c_int32), ("party_from", C.c_char_p),
-                ("party_to", C.c_char_p), ("mode", C.c_int), ("payoffs_dev", C.c_void_p), ("block", C.c_int)]
+                ("party_to", C.c_char_p), ("mode", C.c_int), ("payoffs_dev", C.c_void_p), ("block", C.c_int),
+                ("engine", C.c_int)]
 
 
 class Result(C.Structure):
     _fields_ = [("price", C.c_double), ("std_err", C.c_double), ("sum", C.c_double), ("sum_sq", C.c_double),
                 ("n_paths", C.c_uint64), ("path_dates", C.c_uint64), ("n_slots", C.c_int),
-                ("mode_used", C.c_int), ("ms", C.c_double)]
+                ("mode_used", C.c_int), ("ms", C.c_double), ("gen_ms", C.c_double), ("eval_ms", C.c_double),
+                ("engine_used", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -82,6 +85,7 @@ _sig = {
     "pmc_payoff_load": (_i, [_vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_char_p), _i, C.POINTER(C.c_char_p), _i,
                              C.POINTER(C.c_char_p), _i, C.POINTER(_vp)]),
     "pmc_payoff_free": (None, [_vp]),
+    "pmc_payoff_source": (_i, [_vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "pmc_payoff_get_info": (_i, [_vp, C.POINTER(PayoffInfo)]),
     "pmc_payoff_grid": (_i, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _i, C.POINTER(_i), C.POINTER(_i)]),
     "pmc_price": (_i, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(Gbm), C.POINTER(Opts),
@@ -209,6 +213,14 @@ class Payoff:
         self.ctx.check(lib.pmc_payoff_get_info(self.h, C.byref(o)))
         return {k: getattr(o, k) for k, _ in o._fields_}
 
+    def source(self):
+        """Device source of the compiled engine for this payoff."""
+        n = C.c_size_t()
+        self.ctx.check(lib.pmc_payoff_source(self.h, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value + 1)
+        self.ctx.check(lib.pmc_payoff_source(self.h, buf, n.value + 1, C.byref(n)))
+        return buf.value.decode()
+
     def grid(self, tenv=()):
         t, tp = _i32(tenv if len(tenv) else [0])
         n, hz = C.c_int(), C.c_int()
@@ -238,9 +250,9 @@ def make_model(spot, vol, corr=None, rate=0.03, years_per_day=1.0):
 
 
 def make_opts(n_paths, rng="philox", seed=42, instance=0, precision="f32", t_now=0, parties=("X", "Y"),
-              mode="auto", payoffs=None, block=0):
+              mode="auto", payoffs=None, block=0, engine="auto"):
     o = Opts(int(n_paths), RNG[rng], int(seed), int(instance), PREC[precision], int(t_now),
-             parties[0].encode(), parties[1].encode(), MODE[mode], _ptr(payoffs), int(block))
+             parties[0].encode(), parties[1].encode(), MODE[mode], _ptr(payoffs), int(block), ENGINE[engine])
     return o
 
 

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/pmc.h"
+#include "codegen.h"
 #include "ilc.h"
 #include "kernels.h"
 
@@ -79,6 +80,7 @@ struct pmc_ctx {
   DevBuf blob, partial, result, bad, queue, paths, sobol, chol;
   HostPinned staging;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t evk[3] = {nullptr, nullptr, nullptr};   // around the generation and MC kernels
   int sobol_dims = 0;
   int n_cu = 0;
   std::string device_name;
@@ -89,6 +91,7 @@ struct pmc_ctx {
 struct pmc_payoff {
   Program prog;
   uint64_t hash = 0;
+  mutable JitCache jit;   // compiled-engine kernels, built on first use
 };
 
 // Errors of calls made without a context (payoff loading may run before
@@ -124,6 +127,8 @@ extern "C" int pmc_ctx_create(int device, void* stream, pmc_ctx** out) {
   c->n_cu = prop.multiProcessorCount;
   c->device_name = prop.gcnArchName;
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) return PMC_E_HIP;
+  for (auto& e : c->evk)
+    if (hipEventCreate(&e) != hipSuccess) return PMC_E_HIP;
   *out = c.release();
   return PMC_OK;
 }
@@ -135,6 +140,8 @@ extern "C" void pmc_ctx_destroy(pmc_ctx* c) {
   else (void)hipDeviceSynchronize();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (auto e : c->evk)
+    if (e) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -165,6 +172,24 @@ extern "C" int pmc_payoff_load(pmc_ctx* c, const char* text, size_t len, const c
 }
 
 extern "C" void pmc_payoff_free(pmc_payoff* p) { delete p; }
+
+namespace pmc {
+namespace {
+#include "engine_src.inc"
+}  // namespace
+}  // namespace pmc
+
+extern "C" int pmc_payoff_source(const pmc_payoff* p, char* buf, size_t cap, size_t* len) {
+  if (!p || !len) return PMC_E_ARG;
+  const std::string s = std::string(pmc::kEngineSource) + "\n" + generate_payoff(p->prog);
+  *len = s.size();
+  if (buf && cap) {
+    const size_t n = std::min(cap - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = 0;
+  }
+  return PMC_OK;
+}
 
 extern "C" int pmc_payoff_get_info(const pmc_payoff* p, pmc_payoff_info* o) {
   if (!p || !o) return PMC_E_ARG;
@@ -259,6 +284,7 @@ int check_opts(pmc_ctx* c, const pmc_opts* o) {
   if (o->block != 0 && (o->block % 64 != 0 || o->block > 256 || o->block < 64))
     return fail(c, PMC_E_ARG, "block must be 64, 128, 192 or 256");
   if (o->mode < 0 || o->mode > 2) return fail(c, PMC_E_ARG, "bad mode");
+  if (o->engine < 0 || o->engine > 2) return fail(c, PMC_E_ARG, "bad engine");
   return PMC_OK;
 }
 
@@ -298,6 +324,8 @@ int build_instance(pmc_ctx* c, const Program& P, const pmc_gbm& m, const pmc_opt
   tb.itab.insert(tb.itab.end(), g.daymap.begin(), g.daymap.end());
   d.horizon = g.horizon;
   d.n_slots = (int32_t)g.days.size();
+  d.dense_first = 0;
+  if (!g.days.empty() && g.days.back() - g.days.front() + 1 == (int32_t)g.days.size()) d.dense_first = g.days.front();
   d.t_now = o.t_now;
   // d(day) = exp(-r * day * years_per_day)
   d.disc_off = (int32_t)tb.rtab.size();
@@ -385,6 +413,7 @@ int upload(pmc_ctx* c, const Program& P, const Tables<T>& tb, const pmc_opts& o,
   L.k0 = (uint32_t)(o.seed & 0xFFFFFFFFull);
   L.k1 = (uint32_t)(o.seed >> 32);
   L.n_assets = (int)P.assets.size();
+  L.n_regs = P.n_regs;
   L.ppt = 1;
   if (o.rng == PMC_RNG_SOBOL) {
     int st = ensure_sobol(c, tb.max_dims);
@@ -404,7 +433,7 @@ int factor(pmc_ctx* c, const McLaunch& L, int n_inst, int A) {
 }
 
 int finish(pmc_ctx* c, int n_inst, const std::vector<uint64_t>& n_paths, const std::vector<int>& n_slots,
-           int mode_used, double ms, pmc_result* out) {
+           int mode_used, double ms, pmc_result* out, double gen_ms = 0.0, double eval_ms = 0.0) {
   std::vector<double2> res(n_inst);
   int bad = 0;
   HIP_TRY(c, hipMemcpyAsync(res.data(), c->result.p, n_inst * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
@@ -424,9 +453,30 @@ int finish(pmc_ctx* c, int n_inst, const std::vector<uint64_t>& n_paths, const s
     r.path_dates = n_paths[i] * (uint64_t)n_slots[i];
     r.mode_used = mode_used;
     r.ms = ms;
+    r.gen_ms = gen_ms;
+    r.eval_ms = eval_ms;
     out[i] = r;
   }
   return PMC_OK;
+}
+
+// Launches the Monte Carlo kernel with the requested payoff engine.
+int launch_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec, bool mem, const McLaunch& L,
+                  int grid, int block) {
+  if (o->engine == PMC_ENGINE_INTERPRETER) {
+    HIP_TRY(c, launch_mc(prec, o->rng, mem, L, grid, block, c->stream));
+    return PMC_OK;
+  }
+  hipFunction_t f = nullptr;
+  std::string err;
+  int st = p->jit.get(p->prog, c->device, prec, o->rng, (int)p->prog.assets.size(), mem, &f, err);
+  if (st != PMC_OK) return fail(c, st, err);
+  HIP_TRY(c, launch_mc_jit(f, prec, L, grid, block, c->stream));
+  return PMC_OK;
+}
+
+int engine_used(const pmc_opts* o) {
+  return o->engine == PMC_ENGINE_INTERPRETER ? PMC_ENGINE_INTERPRETER : PMC_ENGINE_COMPILED;
 }
 
 template <typename T>
@@ -469,6 +519,7 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   st = factor(c, L, 1, A);
   if (st != PMC_OK) return st;
   const int prec = sizeof(T) == 8 ? 1 : 0;
+  HIP_TRY(c, hipEventRecord(c->evk[0], c->stream));
   if (mode == PMC_MODE_TWO_PHASE) {
     if (given_paths) {
       L.paths = given_paths;
@@ -479,16 +530,24 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
       L.paths = c->paths.p;
     }
     if (n_slots == 0) L.paths = nullptr;
-    HIP_TRY(c, launch_mc(prec, o->rng, n_slots > 0, L, (int)tiles, block, c->stream));
+    HIP_TRY(c, hipEventRecord(c->evk[1], c->stream));
+    st = launch_engine(c, p, o, prec, n_slots > 0, L, (int)tiles, block);
   } else {
-    HIP_TRY(c, launch_mc(prec, o->rng, false, L, (int)tiles, block, c->stream));
+    HIP_TRY(c, hipEventRecord(c->evk[1], c->stream));
+    st = launch_engine(c, p, o, prec, false, L, (int)tiles, block);
   }
+  if (st != PMC_OK) return st;
+  HIP_TRY(c, hipEventRecord(c->evk[2], c->stream));
   HIP_TRY(c, launch_reduce(L.partial, L.desc, 1, (double2*)c->result.p, c->stream));
   HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
   HIP_TRY(c, hipEventSynchronize(c->ev1));
-  float ms = 0;
+  float ms = 0, gen_ms = 0, eval_ms = 0;
   HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-  return finish(c, 1, {N}, {n_slots}, mode, ms, out);
+  HIP_TRY(c, hipEventElapsedTime(&gen_ms, c->evk[0], c->evk[1]));
+  HIP_TRY(c, hipEventElapsedTime(&eval_ms, c->evk[1], c->evk[2]));
+  st = finish(c, 1, {N}, {n_slots}, mode, ms, out, gen_ms, eval_ms);
+  if (st == PMC_OK) out->engine_used = engine_used(o);
+  return st;
 }
 
 }  // namespace
@@ -617,7 +676,7 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
   L.ppt = ppt;
   L.payoff_out = nullptr;
   bp.L = L;
-  const int occ = mc_occupancy(sizeof(T) == 8 ? 1 : 0, o->rng, A, block);
+  const int occ = mc_occupancy(sizeof(T) == 8 ? 1 : 0, o->rng, A, P.n_regs, block);
   bp.grid = std::max(1, std::min<int>((int)work.size(), c->n_cu * occ));
   bp.block = block; bp.ppt = ppt; bp.n_inst = I;
   bp.n_paths.assign(I, N);
@@ -628,12 +687,13 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
 
 // Enqueue the batched sequence: Cholesky factors, queue reset, persistent
 // MC kernel, per-instance reduction.  Captured once into a graph.
-int batch_enqueue(pmc_ctx* c, const BatchPlan& bp, int prec, int rng, int A) {
+int batch_enqueue(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, const BatchPlan& bp, int prec, int A) {
   int st = factor(c, bp.L, bp.n_inst, A);
   if (st != PMC_OK) return st;
   const McLaunch& L = bp.L;
   HIP_TRY(c, launch_fill_u32(L.queue, 0u, 1, c->stream));
-  HIP_TRY(c, launch_mc(prec, rng, false, L, bp.grid, bp.block, c->stream));
+  st = launch_engine(c, p, o, prec, false, L, bp.grid, bp.block);
+  if (st != PMC_OK) return st;
   HIP_TRY(c, launch_reduce(L.partial, L.desc, bp.n_inst, (double2*)c->result.p, c->stream));
   return PMC_OK;
 }
@@ -643,7 +703,7 @@ int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_op
   const int A = (int)p->prog.assets.size();
   std::ostringstream key;
   key << p->hash << ':' << bp.n_inst << ':' << bp.grid << ':' << bp.block << ':' << bp.ppt << ':' << bp.L.n_work
-      << ':' << prec << ':' << o->rng << ':' << c->blob.p << ':' << c->partial.p << ':' << c->result.p << ':'
+      << ':' << prec << ':' << o->rng << ':' << o->engine << ':' << c->blob.p << ':' << c->partial.p << ':' << c->result.p << ':'
       << c->chol.p << ':' << c->sobol.p << ':' << (const void*)bp.L.desc << ':' << (const void*)bp.L.work;
   if (c->graph.key != key.str()) {
     if (c->graph.exec) { (void)hipGraphExecDestroy(c->graph.exec); c->graph.exec = nullptr; }
@@ -656,8 +716,14 @@ int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_op
     }
     hipStream_t saved = c->stream;
     c->stream = cap;
+    if (o->engine != PMC_ENGINE_INTERPRETER) {   // compile outside the capture
+      hipFunction_t f = nullptr;
+      std::string err;
+      int jst = p->jit.get(p->prog, c->device, prec, o->rng, A, false, &f, err);
+      if (jst != PMC_OK) { c->stream = saved; if (own) (void)hipStreamDestroy(cap); return fail(c, jst, err); }
+    }
     HIP_TRY(c, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    int st = batch_enqueue(c, bp, prec, o->rng, A);
+    int st = batch_enqueue(c, p, o, bp, prec, A);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(cap, &graph);
     c->stream = saved;
@@ -680,7 +746,7 @@ int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_op
 std::string tune_key(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc_opts* o) {
   std::ostringstream k;
   k << c->device_name << '/' << std::hex << p->hash << std::dec << '/' << b->n_inst << '/' << o->n_paths << '/'
-    << o->precision << '/' << o->rng;
+    << o->precision << '/' << o->rng << '/' << o->engine;
   return k.str();
 }
 
@@ -714,7 +780,10 @@ extern "C" int pmc_price_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch*
   float ms = 0;
   st = batch_run(c, p, bp, o, &ms);
   if (st != PMC_OK) return st;
-  return finish(c, bp.n_inst, bp.n_paths, bp.n_slots, PMC_MODE_FUSED, ms, out);
+  st = finish(c, bp.n_inst, bp.n_paths, bp.n_slots, PMC_MODE_FUSED, ms, out, 0.0, ms);
+  if (st == PMC_OK)
+    for (int i = 0; i < bp.n_inst; ++i) out[i].engine_used = engine_used(o);
+  return st;
 }
 
 extern "C" int pmc_autotune_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc_gbm* m,

@@ -442,6 +442,7 @@ int compile(const char* text, size_t len, const std::vector<std::string>& assets
   en.compute_need(root);
   en.gen(root, 0);
   en.emit(OP_HALT, kTrash, 0, 0, 0);
+  en.emit(OP_HALT, kTrash, 0, 0, 0);   // padding: the interpreter prefetches pc + 1
   P.n_regs = en.max_reg + 1;
   P.loop_depth = en.max_depth;
   if (P.n_regs > kMaxRegs) {

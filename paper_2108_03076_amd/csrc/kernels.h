@@ -28,10 +28,13 @@ struct McLaunch {
   uint32_t k0, k1;            // Philox key
   int ppt;                    // paths per thread per item
   int n_assets;
+  int n_regs;                 // registers the program uses (selects the file size)
 };
 
 hipError_t launch_mc(int precision, int rng, bool from_memory, const McLaunch& a, int grid, int block,
                      hipStream_t s);
+// Launch of a run-time compiled Monte Carlo kernel (generated payoff).
+hipError_t launch_mc_jit(hipFunction_t f, int precision, const McLaunch& a, int grid, int block, hipStream_t s);
 hipError_t launch_pathgen(int precision, int rng, const McLaunch& a, void* paths, uint32_t* words,
                           void* normals, uint32_t n_paths, int block, hipStream_t s);
 hipError_t launch_reduce(const double2* partial, const InstDesc* desc, int n_inst, double2* out,
@@ -39,6 +42,6 @@ hipError_t launch_reduce(const double2* partial, const InstDesc* desc, int n_ins
 hipError_t launch_cholesky(const double* a, double* l, int* bad, int n, int m, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s);
 // Largest resident blocks per CU for the persistent MC kernel.
-int mc_occupancy(int precision, int rng, int n_assets, int block);
+int mc_occupancy(int precision, int rng, int n_assets, int n_regs, int block);
 
 }  // namespace pmc

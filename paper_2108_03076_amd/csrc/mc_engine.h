@@ -1,0 +1,522 @@
+// Device engine of the Monte Carlo pricer: random streams, normals, path
+// sources, the bytecode interpreter, reductions and the kernel body that
+// drives them.  Included by the static kernels (mc_kernels.hip) and, as text,
+// by the payoff code generator, whose run-time compiled kernels reuse this
+// body with a generated payoff function in place of the interpreter.
+#pragma once
+#include "pmc_device.h"
+
+namespace pmc {
+namespace eng {
+
+// ------------------------------------------------------------ Philox ------
+// Philox4x32-10 (Salmon et al., SC'11): two 32x32 multiplications per round,
+// swap-and-xor with the key, Weyl key bump between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// ---------------------------------------------- uniforms and normals -----
+template <typename T> struct Num;
+
+// FP32: u = (x>>9 + 1/2) 2^-23 (exact in binary32); Phi^-1 by AS241's
+// 7-digit variant PPND7 (Wichura 1988).
+template <> struct Num<float> {
+  static __device__ __forceinline__ float uniform(uint32_t x) {
+    return fmaf((float)(x >> 9), 0x1p-23f, 0x1p-24f);
+  }
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ float normal(float p) {
+    const float q = p - 0.5f;
+    // central region |q| <= 0.425
+    const float r = 0.180625f - q * q;
+    const float nc = q * fmaf(fmaf(fmaf(59.109374720f, r, 159.29113202f), r, 50.434271938f), r, 3.3871327179f);
+    const float dc = fmaf(fmaf(fmaf(67.187563600f, r, 78.757757664f), r, 17.895169469f), r, 1.0f);
+    // tails: r = sqrt(-log(min(p, 1-p))); 1-p is exact for our uniforms
+    const float pt = fminf(p, 1.0f - p);
+    const float rt = __builtin_sqrtf(-__logf(pt));
+    float s = rt - 1.6f;
+    float nt = fmaf(fmaf(fmaf(0.17023821103f, s, 1.3067284816f), s, 2.7568153900f), s, 1.4234372777f);
+    float dt = fmaf(fmaf(0.12021132975f, s, 0.73700164250f), s, 1.0f);
+    const bool far = rt > 5.0f;
+    if (__any(far)) {   // min(p,1-p) < e^-25: unreachable for 23-bit uniforms, kept for completeness
+      const float e = rt - 5.0f;
+      const float ne = fmaf(fmaf(fmaf(0.017337203997f, e, 0.42868294337f), e, 3.0812263860f), e, 6.6579051150f);
+      const float de = fmaf(fmaf(0.012258202635f, e, 0.24197894225f), e, 1.0f);
+      nt = far ? ne : nt;
+      dt = far ? de : dt;
+    }
+    const bool central = fabsf(q) <= 0.425f;
+    const float num = central ? nc : copysignf(nt, q);
+    const float den = central ? dc : dt;
+    return num * rcp(den);
+  }
+  static __device__ __forceinline__ float expv(float x) { return __expf(x); }
+  static __device__ __forceinline__ float div(float a, float b) { return a * rcp(b); }
+};
+
+// FP64: u = (x + 1/2) 2^-32 (exact); Phi^-1 by AS241 PPND16.
+template <> struct Num<double> {
+  static __device__ __forceinline__ double uniform(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
+  static __device__ double normal(double p) {
+    const double q = p - 0.5;
+    if (fabs(q) <= 0.425) {
+      const double r = 0.180625 - q * q;
+      const double n = ((((((2.5090809287301226727e+3 * r + 3.3430575583588128105e+4) * r +
+                             6.7265770927008700853e+4) * r + 4.5921953931549871457e+4) * r +
+                           1.3731693765509461125e+4) * r + 1.9715909503065514427e+3) * r +
+                         1.3314166789178437745e+2) * r + 3.3871328727963666080e0;
+      const double d = ((((((5.2264952788528545610e+3 * r + 2.8729085735721942674e+4) * r +
+                             3.9307895800092710610e+4) * r + 2.1213794301586595867e+4) * r +
+                           5.3941960214247511077e+3) * r + 6.8718700749205790830e+2) * r +
+                         4.2313330701600911252e+1) * r + 1.0;
+      return q * n / d;
+    }
+    double r = q < 0 ? p : 1.0 - p;
+    r = sqrt(-log(r));
+    double v;
+    if (r <= 5.0) {
+      r -= 1.6;
+      const double n = ((((((7.74545014278341407640e-4 * r + 2.27238449892691845833e-2) * r +
+                             2.41780725177450611770e-1) * r + 1.27045825245236838258e0) * r +
+                           3.64784832476320460504e0) * r + 5.76949722146069140550e0) * r +
+                         4.63033784615654529590e0) * r + 1.42343711074968357734e0;
+      const double d = ((((((1.05075007164441684324e-9 * r + 5.47593808499534494600e-4) * r +
+                             1.51986665636164571966e-2) * r + 1.48103976427480074590e-1) * r +
+                           6.89767334985100004550e-1) * r + 1.67638483018380384940e0) * r +
+                         2.05319162663775882187e0) * r + 1.0;
+      v = n / d;
+    } else {
+      r -= 5.0;
+      const double n = ((((((2.01033439929228813265e-7 * r + 2.71155556874348757815e-5) * r +
+                             1.24266094738807843860e-3) * r + 2.65321895265761230930e-2) * r +
+                           2.96560571828504891230e-1) * r + 1.78482653991729133580e0) * r +
+                         5.46378491116411436990e0) * r + 6.65790464350110377720e0;
+      const double d = ((((((2.04426310338993978564e-15 * r + 1.42151175831644588870e-7) * r +
+                             1.84631831751005468180e-5) * r + 7.86869131145613259100e-4) * r +
+                           1.48753612908506148525e-2) * r + 1.36929880922735805310e-1) * r +
+                         5.99832206555887937690e-1) * r + 1.0;
+      v = n / d;
+    }
+    return q < 0 ? -v : v;
+  }
+  static __device__ __forceinline__ double expv(double x) { return exp(x); }
+  static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+};
+
+template <typename T>
+struct Args {
+  const Instr* code;
+  const T* consts;
+  const InstDesc* desc;
+  const int32_t* itab;
+  const T* rtab;
+  const double* chol;
+  const uint32_t* sobol;
+  int sobol_bits;
+  const int2* work;
+  int n_work;
+  uint32_t* queue;
+  double2* partial;
+  T* payoff_out;
+  const T* paths;
+  uint32_t k0, k1;
+  int ppt;
+  int n_assets;
+};
+
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Read-only tables (bytecode, descriptors, time tables, discount factors,
+// model constants, direction numbers) are read through the constant address
+// space so that uniform reads become scalar loads through the scalar cache.
+template <typename T>
+using kptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ kptr<T> K(const T* p) { return (kptr<T>)p; }
+
+__device__ __forceinline__ InstDesc load_desc(const InstDesc* base, int i) {
+  InstDesc d;
+  kptr<int32_t> src = K(reinterpret_cast<const int32_t*>(base + i));
+  int32_t* dst = reinterpret_cast<int32_t*>(&d);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(InstDesc) / 4); ++k) dst[k] = src[k];
+  return d;
+}
+
+// ------------------------------------------------------- path sources -----
+// Per-instance model constants, uniform across the wave.
+template <typename T, int A>
+struct Model {
+  T mu[A], sig[A], s0[A];
+  T L[A][A];
+  __device__ __forceinline__ void load(const Args<T>& g, const InstDesc& D) {
+    kptr<T> m = K(g.rtab) + D.model_off;
+#pragma unroll
+    for (int a = 0; a < A; ++a) { mu[a] = m[a]; sig[a] = m[A + a]; s0[a] = m[2 * A + a]; }
+    kptr<double> l = K(g.chol) + D.chol_off;
+#pragma unroll
+    for (int i = 0; i < A; ++i)
+#pragma unroll
+      for (int j = 0; j < A; ++j) L[i][j] = (T)l[i * A + j];
+  }
+};
+
+// Generates the path of one lane slot by slot into the window.
+template <typename T, int RNG, int A>
+struct GenSource {
+  static constexpr int WS = kWindow / A;   // slots held in the window
+  T x[A];
+  int base;        // first slot in the window (uniform), -1 if empty
+  int next_slot;   // next slot to generate (uniform)
+  uint32_t blk;    // Philox block held in buf (uniform)
+  uint32_t buf[4];
+  uint32_t path, gray;
+  uint32_t k0, k1, inst;
+  int n_slots, sobol_bits;
+  kptr<uint32_t> sobol;
+  kptr<T> slotc;
+  kptr<T> spotp;
+  Model<T, A> M;
+
+  __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p) {
+    path = p; gray = p ^ (p >> 1);
+    k0 = g.k0; k1 = g.k1; inst = d.instance;
+    n_slots = d.n_slots; sobol_bits = g.sobol_bits; sobol = K(g.sobol);
+    M.load(g, d);
+    slotc = K(g.rtab) + d.slot_off;
+    spotp = K(g.rtab) + d.model_off + 2 * A;
+    base = -1; next_slot = 0; blk = 0xFFFFFFFFu;
+#pragma unroll
+    for (int a = 0; a < A; ++a) x[a] = T(0);
+  }
+
+  __device__ __forceinline__ uint32_t word(uint32_t w) {
+    if (RNG == 0) {
+      const uint32_t b = w >> 2;
+      if (b != blk) {
+        philox4x32_10(path, b, inst, 0u, k0, k1, buf);
+        blk = b;
+      }
+      const uint32_t j = w & 3u;
+      return j == 0 ? buf[0] : j == 1 ? buf[1] : j == 2 ? buf[2] : buf[3];
+    } else {
+      kptr<uint32_t> v = sobol + (size_t)w * 32u;
+      uint32_t acc = 0;
+      for (int b = 0; b < sobol_bits; ++b) acc ^= v[b] & (0u - ((gray >> b) & 1u));
+      return acc;
+    }
+  }
+
+  // one GBM step to slot q (all assets); optionally record words/normals
+  __device__ __forceinline__ void step(int q, uint32_t* wout, T* zout, uint32_t npath) {
+    T z[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      const uint32_t w = (uint32_t)(q * A + a);
+      const uint32_t x32 = word(w);
+      z[a] = Num<T>::normal(Num<T>::uniform(x32));
+      if (wout) wout[(size_t)w * npath + path] = x32;
+      if (zout) zout[(size_t)w * npath + path] = z[a];
+    }
+    const T dt = slotc[2 * q], sdt = slotc[2 * q + 1];
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      T wa = T(0);
+#pragma unroll
+      for (int k = 0; k <= a; ++k) wa += M.L[a][k] * z[k];
+      x[a] = x[a] + M.mu[a] * dt + (M.sig[a] * sdt) * wa;
+    }
+  }
+
+  __device__ __forceinline__ void refill(T (&win)[kWindow], int s) {
+    if (s < next_slot) {            // backward read: regenerate from the spot
+#pragma unroll
+      for (int a = 0; a < A; ++a) x[a] = T(0);
+      next_slot = 0;
+    }
+    while (next_slot < s) { step(next_slot, nullptr, nullptr, 0); ++next_slot; }
+    const int cnt = min(WS, n_slots - s);
+#pragma unroll 1
+    for (int j = 0; j < cnt; ++j) {
+      step(s + j, nullptr, nullptr, 0);
+#pragma unroll
+      for (int a = 0; a < A; ++a) win[(j * A + a) & (kWindow - 1)] = M.s0[a] * Num<T>::expv(x[a]);
+    }
+    next_slot = s + cnt;
+    base = s;
+  }
+
+  __device__ __forceinline__ T read(T (&win)[kWindow], int slot, int a) {
+    if (slot < base || slot >= base + WS || base < 0) refill(win, slot);
+    const int i = uni((slot - base) * A + a) & (kWindow - 1);
+    return win[i];
+  }
+  __device__ __forceinline__ T spot(int a) const { return spotp[a]; }
+};
+
+// Reads stored prices [slot][asset][path] through the same window.
+template <typename T, int A>
+struct MemSource {
+  static constexpr int WS = kWindow / A;
+  int base, n_slots;
+  uint32_t path, n_paths;
+  const T* paths;
+  kptr<T> spotp;
+
+  __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p) {
+    path = p; n_paths = d.n_paths; n_slots = d.n_slots; base = -1;
+    paths = g.paths;
+    spotp = K(g.rtab) + d.model_off + 2 * A;
+  }
+  __device__ __forceinline__ void refill(T (&win)[kWindow], int s) {
+    const int last = n_slots - 1;
+#pragma unroll
+    for (int j = 0; j < WS; ++j) {
+      const int q = min(s + j, last);
+#pragma unroll
+      for (int a = 0; a < A; ++a)
+        win[j * A + a] = paths[((size_t)q * A + a) * n_paths + path];
+    }
+    base = s;
+  }
+  __device__ __forceinline__ T read(T (&win)[kWindow], int slot, int a) {
+    if (slot < base || slot >= base + WS || base < 0) refill(win, slot);
+    const int i = uni((slot - base) * A + a) & (kWindow - 1);
+    return win[i];
+  }
+  __device__ __forceinline__ T spot(int a) const { return spotp[a]; }
+};
+
+// An observable of a model asset on a day: the spot for day <= 0 (flat
+// history), else the simulated price of the day's slot.
+template <typename T, class Src>
+__device__ __forceinline__ T read_obs(Src& src, T (&win)[kWindow], const InstDesc& D, kptr<int32_t> dm, int day,
+                                      int asset) {
+  if (day <= 0) return src.spot(asset);
+  const int s = D.dense_first > 0 ? min(day - D.dense_first, D.n_slots - 1) : uni(dm[min(day, D.horizon)]);
+  return s < 0 ? src.spot(asset) : src.read(win, s, asset);
+}
+
+// ------------------------------------------------------- interpreter ------
+template <typename T, int NR, class Src>
+__device__ __forceinline__ T interpret(const Args<T>& g, const InstDesc& D, Src& src, int* frames) {
+  T R[NR];
+  T win[kWindow];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) R[i] = T(0);
+#pragma unroll
+  for (int i = 0; i < kWindow; ++i) win[i] = T(0);
+  kptr<int32_t> tt = K(g.itab) + D.tt_off;
+  kptr<int32_t> dm = K(g.itab) + D.daymap_off;
+  kptr<T> consts = K(g.consts);
+  kptr<T> rt = K(g.rtab);
+  kptr<int32_t> it = K(g.itab);
+  kptr<uint32_t> code = K(reinterpret_cast<const uint32_t*>(g.code));
+  int pc = 0, t0 = 0;
+  int f_top = 0, f_rem = 0, f_t0 = 0, depth = 0;
+  uint32_t w0 = (uint32_t)uni((int)code[0]);
+  int imm = uni((int)code[1]);
+  for (;;) {
+    // prefetch the next instruction (the program ends with two HALTs)
+    const uint32_t n0 = (uint32_t)uni((int)code[2 * pc + 2]);
+    const int nimm = uni((int)code[2 * pc + 3]);
+    const int op = w0 & 0xff, a = (w0 >> 16) & (NR - 1), b = (w0 >> 24) & (NR - 1);
+    const int d = (w0 >> 8) & (NR - 1);
+    const int ai = (w0 >> 16) & 0xff;  // asset / party-pair operand
+    const int next = pc + 1;
+    ++pc;
+    if (op == OP_HALT) break;
+    const T ra = R[a], rb = R[b];
+    T v = T(0);
+    switch (op) {
+      case OP_CONST: v = consts[imm]; break;
+      case OP_PARAM: v = rt[D.param_off + imm]; break;
+      case OP_MODEL: v = read_obs(src, win, D, dm, tt[imm] + t0, ai); break;
+      case OP_TEXPR: v = (T)(tt[imm] + t0); break;
+      case OP_NOW: v = (T)D.t_now; break;
+      case OP_PAYOFF: {
+        const int day = min(max(tt[imm] + t0, 0), D.horizon);
+        v = (T)it[D.sign_off + ai] * rt[D.disc_off + day];
+        break;
+      }
+      case OP_ADD: v = ra + rb; break;
+      case OP_SUB: v = ra - rb; break;
+      case OP_MUL: v = ra * rb; break;
+      case OP_DIV: v = Num<T>::div(ra, rb); break;
+      case OP_MIN: v = fmin(ra, rb); break;
+      case OP_MAX: v = fmax(ra, rb); break;
+      case OP_LT: v = ra < rb ? T(1) : T(0); break;
+      case OP_LE: v = ra <= rb ? T(1) : T(0); break;
+      case OP_EQ: v = ra == rb ? T(1) : T(0); break;
+      case OP_AND: v = (ra != T(0) && rb != T(0)) ? T(1) : T(0); break;
+      case OP_OR: v = (ra != T(0) || rb != T(0)) ? T(1) : T(0); break;
+      case OP_NEG: v = -ra; break;
+      case OP_NOT: v = ra == T(0) ? T(1) : T(0); break;
+      case OP_SEL: v = ra != T(0) ? rb : R[imm & (NR - 1)]; break;
+      case OP_JNONE:
+        if (!__any(ra != T(0))) pc = imm;
+        break;
+      case OP_JALL:
+        if (__all(ra != T(0))) pc = imm;
+        break;
+      case OP_LOOP:
+        if (depth > 0) {
+          frames[3 * depth - 3] = f_top; frames[3 * depth - 2] = f_rem; frames[3 * depth - 1] = f_t0;
+        }
+        ++depth;
+        f_top = pc; f_rem = tt[imm]; f_t0 = t0;
+        break;
+      case OP_LTAKE: {
+        const bool take = ra == T(0) && R[d] != T(0);
+        v = take ? T(1) : T(0);
+        if (!__any(take)) pc = imm;
+        break;
+      }
+      case OP_LMERGE: v = ra != T(0) ? rb : R[d]; break;
+      case OP_LDONE: v = (R[d] != T(0) || ra != T(0)) ? T(1) : T(0); break;
+      case OP_LNEXT:
+        if (__all(ra != T(0))) {
+          pc = imm;
+        } else if (f_rem > 0) {
+          --f_rem; ++t0; pc = f_top;
+        }
+        break;
+      case OP_LELSE: v = ra != T(0) ? R[d] : rb; break;
+      case OP_LEND:
+        t0 = f_t0;
+        --depth;
+        if (depth > 0) {
+          f_top = uni(frames[3 * depth - 3]); f_rem = uni(frames[3 * depth - 2]); f_t0 = uni(frames[3 * depth - 1]);
+        }
+        break;
+      default: break;
+    }
+    R[d] = v;
+    if (pc == next) {
+      w0 = n0; imm = nimm;
+    } else {
+      w0 = (uint32_t)uni((int)code[2 * pc]);
+      imm = uni((int)code[2 * pc + 1]);
+    }
+  }
+  return R[0];
+}
+
+// ------------------------------------------------------ reductions --------
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Block sums of (s, ss); thread 0 gets the result.  red: 2 * (blockDim/64)
+__device__ __forceinline__ void block_sum2(double& s, double& ss, double* red) {
+  s = wave_sum(s);
+  ss = wave_sum(ss);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) { red[2 * wv] = s; red[2 * wv + 1] = ss; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s = 0; ss = 0;
+    for (int i = 0; i < nw; ++i) { s += red[2 * i]; ss += red[2 * i + 1]; }
+  }
+  __syncthreads();
+}
+
+// ----------------------------------------------------------- kernels ------
+// Work items are (instance, tile); a tile is ppt * blockDim paths of one
+// instance.  Non-persistent launches take item = blockIdx.x of instance 0;
+// persistent launches pull items from an atomic counter until none is left.
+// Evaluator policy that interprets the loaded bytecode with an NR-entry
+// register file.
+template <int NR>
+struct Interp {
+  template <typename T, class Src>
+  static __device__ __forceinline__ T run(const Args<T>& g, const InstDesc& D, Src& src, int* frames) {
+    return interpret<T, NR>(g, D, src, frames);
+  }
+};
+
+template <typename T, int RNG, int A, bool MEM, class Eval>
+__device__ __forceinline__ void mc_body(const Args<T>& g) {
+  __shared__ double red[8];
+  __shared__ int frames_all[4][3 * kMaxLoopDepth];
+  __shared__ int item_s;
+  int* frames = frames_all[threadIdx.x >> 6];
+  int item = blockIdx.x;
+  for (;;) {
+    if (g.queue) {
+      if (threadIdx.x == 0) item_s = (int)atomicAdd(g.queue, 1u);
+      __syncthreads();
+      item = item_s;
+      __syncthreads();
+    }
+    if (item >= g.n_work) break;
+    int2 wi = make_int2(0, item);
+    if (g.work) {
+      kptr<int> wp = K(reinterpret_cast<const int*>(g.work)) + 2 * item;
+      wi = make_int2(wp[0], wp[1]);
+    }
+    const InstDesc D = load_desc(g.desc, wi.x);
+    double s = 0.0, ss = 0.0;
+    for (int r = 0; r < g.ppt; ++r) {
+      const uint32_t path = ((uint32_t)wi.y * (uint32_t)g.ppt + (uint32_t)r) * blockDim.x + threadIdx.x;
+      const bool valid = path < D.n_paths;
+      const uint32_t p = valid ? path : D.n_paths - 1;
+      T v;
+      if (MEM) {
+        MemSource<T, A> src;
+        src.init(g, D, p);
+        v = Eval::template run<T>(g, D, src, frames);
+      } else {
+        GenSource<T, RNG, A> src;
+        src.init(g, D, p);
+        v = Eval::template run<T>(g, D, src, frames);
+      }
+      if (valid) {
+        const double x = (double)v;
+        s += x; ss += x * x;
+        if (g.payoff_out) g.payoff_out[path] = v;
+      }
+    }
+    block_sum2(s, ss, red);
+    if (threadIdx.x == 0) g.partial[D.first_item + wi.y] = make_double2(s, ss);
+    if (!g.queue) break;
+  }
+}
+
+// Two-phase path generation: stored prices [slot][asset][path].
+template <typename T, int RNG, int A>
+__device__ __forceinline__ void pathgen_body(const Args<T>& g, T* out, uint32_t* wout, T* zout, uint32_t n_paths) {
+  const uint32_t path = blockIdx.x * blockDim.x + threadIdx.x;
+  if (path >= n_paths) return;
+  const InstDesc D = load_desc(g.desc, 0);
+  GenSource<T, RNG, A> src;
+  src.init(g, D, path);
+  for (int q = 0; q < D.n_slots; ++q) {
+    src.step(q, wout, zout, n_paths);
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+      out[((size_t)q * A + a) * n_paths + path] = src.M.s0[a] * Num<T>::expv(src.x[a]);
+  }
+}
+
+// Deterministic per-instance sum of the work-item partials: one block per
+// instance, fixed summation order.
+
+}  // namespace eng
+}  // namespace pmc

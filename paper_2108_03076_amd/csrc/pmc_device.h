@@ -44,9 +44,12 @@ enum Op : uint8_t {
   OP_COUNT
 };
 
-constexpr int kMaxRegs = 24;           // user registers R[0 .. kMaxRegs-1]
-constexpr int kTrash = kMaxRegs;       // write sink
-constexpr int kRegFile = 32;            // registers per lane (power of two: indices are masked)
+// Register files hold 8 or 32 values per lane (the kernel is specialised by
+// the program's register count); indices are masked to the file size, so the
+// write sink 31 lands on the file's last register in either size.
+constexpr int kMaxRegs = 31;           // user registers R[0 .. kMaxRegs-1]
+constexpr int kTrash = 31;             // write sink
+constexpr int kRegFile = 32;           // largest register file
 constexpr int kMaxLoopDepth = 8;
 constexpr int kWindow = 16;            // cached path values per lane
 
@@ -68,7 +71,8 @@ struct InstDesc {
   uint32_t n_paths;
   uint32_t n_tiles;    // work items of this instance
   int32_t first_item;  // index of its first partial-sum slot
-  int32_t pad;
+  int32_t dense_first; // > 0: the slots are the consecutive days dense_first ..
+                       // dense_first + n_slots - 1 (no day map lookup needed)
 };
 
 }  // namespace pmc

@@ -100,15 +100,18 @@ def test_payoffs_on_stored_paths(name):
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("mode", ["fused", "two_phase"])
-def test_price_matches_oracle(name, mode):
+@pytest.mark.parametrize("engine", ["interpreter", "compiled"])
+def test_price_matches_oracle(name, mode, engine):
     import paper_2108_03076_amd as P
     cfg = CASES[name]
     n = 4000 if cfg.precision == "f32" else 1 << 14
-    print(f"[parity] price {name} {mode} n={n}", flush=True)
+    print(f"[parity] price {name} {mode} {engine} n={n}", flush=True)
     pay = gpu_payoff(cfg)
     dt = torch.float64 if cfg.precision == "f64" else torch.float32
     out = torch.empty(n, dtype=dt, device="cuda")
-    r = P.price(pay, cfg.tenv, cfg.params, **model_kw(cfg), **opts_kw(cfg, n, mode=mode, payoffs=out))
+    r = P.price(pay, cfg.tenv, cfg.params, **model_kw(cfg),
+                **opts_kw(cfg, n, mode=mode, payoffs=out, engine=engine))
+    assert r["engine_used"] == (1 if engine == "interpreter" else 2)
     prob = oracle_problem(cfg)
     ids = np.arange(n)
     ref_pay = prob.payoffs(ids)
@@ -153,8 +156,9 @@ def test_c3_full_size_sampled_paths():
     print("[parity] C3 full size", flush=True)
     pay = gpu_payoff(cfg)
     out = torch.empty(n, dtype=torch.float32, device="cuda")
-    for mode in ("fused", "two_phase"):
-        r = P.price(pay, cfg.tenv, cfg.params, **model_kw(cfg), **opts_kw(cfg, n, mode=mode, payoffs=out))
+    for mode, engine in (("fused", "compiled"), ("two_phase", "compiled"), ("fused", "interpreter")):
+        r = P.price(pay, cfg.tenv, cfg.params, **model_kw(cfg),
+                    **opts_kw(cfg, n, mode=mode, payoffs=out, engine=engine))
         gpu = out.double().cpu().numpy()
         ids = sample_ids(n, 48)
         prob = oracle_problem(cfg)
@@ -190,7 +194,8 @@ def test_c2_full_size_sampled_paths():
     assert 70 < r["price"] < 95
 
 
-def test_batch_matches_single_and_oracle():
+@pytest.mark.parametrize("engine", ["interpreter", "compiled"])
+def test_batch_matches_single_and_oracle(engine):
     import paper_2108_03076_amd as P
     from oracle.mc import estimate
     cfg = _small(W.C4)
@@ -198,11 +203,13 @@ def test_batch_matches_single_and_oracle():
     K = np.linspace(90, 110, T.size)
     B = np.linspace(60, 95, T.size)
     n = 1500
-    print("[parity] batch", flush=True)
+    print(f"[parity] batch {engine}", flush=True)
     pay = gpu_payoff(cfg)
-    res = P.price_batch(pay, T.reshape(-1, 1), np.stack([K, B], 1), **model_kw(cfg), **opts_kw(cfg, n))
+    res = P.price_batch(pay, T.reshape(-1, 1), np.stack([K, B], 1), **model_kw(cfg),
+                        **opts_kw(cfg, n, engine=engine))
     for i in range(T.size):
-        one = P.price(pay, [int(T[i])], [K[i], B[i]], **model_kw(cfg), **opts_kw(cfg, n, instance=i))
+        one = P.price(pay, [int(T[i])], [K[i], B[i]], **model_kw(cfg),
+                      **opts_kw(cfg, n, instance=i, engine=engine))
         assert res[i]["price"] == pytest.approx(one["price"], rel=1e-12, abs=1e-12)
         prob = oracle_problem(cfg, tenv={"T": int(T[i])}, params=[K[i], B[i]], instance=i)
         ref, se = estimate(prob.payoffs(np.arange(n)))
@@ -230,6 +237,22 @@ def test_batch_per_instance_model_and_determinism():
                               corr=corr[i], instance=i)
         ref, se = estimate(prob.payoffs(np.arange(n)))
         assert abs(a[i]["price"] - ref) <= 0.1 * se + 1e-9, (i, a[i]["price"], ref, se)
+
+
+def test_compiled_and_interpreted_payoffs_are_identical():
+    """Both engines read the same path values and apply the same binary32
+    operations, so per-path payoffs agree bit for bit."""
+    import paper_2108_03076_amd as P
+    for cfg in (_small(W.C3, tenv=[100]), W.C2, W.C1):
+        n = 3000
+        pay = gpu_payoff(cfg)
+        dt = torch.float64 if cfg.precision == "f64" else torch.float32
+        outs = []
+        for engine in ("interpreter", "compiled"):
+            out = torch.empty(n, dtype=dt, device="cuda")
+            P.price(pay, cfg.tenv, cfg.params, **model_kw(cfg), **opts_kw(cfg, n, payoffs=out, engine=engine))
+            outs.append(out.cpu().numpy())
+        assert np.array_equal(outs[0], outs[1]), cfg.name
 
 
 def test_gpu_cholesky_matches_oracle():
