@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="headline workload only, no CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also copy 256 MiB device-to-device three times (a known-size kernel for "
+                         "scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -99,6 +102,13 @@ def main():
 
     base = json.load(open(os.path.join(ROOT, "BASELINE.json")))
     ctx = P.Context(0)
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def setup(cfg):
         pay = P.Payoff(ctx, cfg.il, cfg.asset_labels, cfg.param_labels, cfg.tvars)
@@ -109,7 +119,8 @@ def main():
     # ---------------- headline: C2 worst-of autocall, fused ----------------
     c2 = W.C2
     pay2, kw2 = setup(c2)
-    step = lambda: P.price(pay2, c2.tenv, c2.params, **kw2)
+    pricer = P.Pricer(pay2, c2.tenv, c2.params, **kw2)
+    step = lambda: pricer().as_dict()
     sec, outs = time_steps(step, args.steps, args.warmup)
     D = outs[-1]["n_slots"]
     pd = c2.n_paths * D

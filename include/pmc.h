@@ -263,14 +263,16 @@ typedef struct pmc_train_opts {
   double beta1, beta2, eps;
 } pmc_train_opts;
 /* One pass over n samples (x_dev [n][n_in] float, raw inputs; y_dev [n]
- * float prices) in order; *mean_loss receives the mean squared error of the
- * scaled target over the pass. */
+ * float prices) in order, one Adam step per full batch (a trailing partial
+ * batch is skipped); *mean_loss receives the mean squared error of the
+ * scaled target over the pass.  o->batch must be a multiple of 64. */
 int pmc_mlp_train_epoch(pmc_mlp* m, const float* x_dev, const float* y_dev, int64_t n,
                         const pmc_train_opts* o, double* mean_loss);
 /* Forward pass: y_dev[n] prices (float) for raw inputs x_dev[n][n_in]. */
 int pmc_mlp_infer(pmc_mlp* m, const float* x_dev, float* y_dev, int64_t n);
-/* Loss and gradients of the mean squared error over n samples at the
- * current weights (FP32 gradients, host out, same order as get_params). */
+/* Loss and gradients of the mean squared error over n samples (1 <= n <=
+ * 65536) at the current weights (FP32 gradients, host out, same order as
+ * get_params). */
 int pmc_mlp_loss_grad(pmc_mlp* m, const float* x_dev, const float* y_dev, int64_t n,
                       double* loss, float* grad_out);
 

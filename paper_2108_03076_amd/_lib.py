@@ -266,6 +266,78 @@ def price(payoff: Payoff, tenv=(), params=(), *, spot, vol, corr=None, rate=0.03
     return r.as_dict()
 
 
+class Pricer:
+    """A prepared pmc_price call: the arguments are marshalled once and each
+    call runs one complete pricing through the C ABI (for timing loops)."""
+
+    def __init__(self, payoff: Payoff, tenv=(), params=(), *, spot, vol, corr=None, rate=0.03,
+                 years_per_day=1.0, **opts):
+        self.payoff = payoff
+        self.g, self._keep = make_model(spot, vol, corr, rate, years_per_day)
+        self.o = make_opts(**opts)
+        self.t, tp = _i32(tenv if len(tenv) else [0])
+        self.p, pp = _dbl(params if len(params) else [0.0])
+        self.r = Result()
+        self._args = (payoff.ctx.h, payoff.h, tp, pp, C.byref(self.g), C.byref(self.o), C.byref(self.r))
+
+    def __call__(self):
+        st = lib.pmc_price(*self._args)
+        if st != 0:
+            self.payoff.ctx.check(st)
+        return self.r
+
+
+class Surrogate:
+    """The learned surrogate (pmc_mlp_*): an MLP n_in -> width x 3 -> 1 trained
+    and evaluated by the library's BF16 matrix-core kernels."""
+
+    def __init__(self, ctx: Context, lo, hi, y_scale=100.0, width=256, seed=0):
+        lo_a, lo_p = _dbl(lo)
+        hi_a, hi_p = _dbl(hi)
+        self.ctx, self.n_in = ctx, int(lo_a.size)
+        h = C.c_void_p()
+        ctx.check(lib.pmc_mlp_create(ctx.h, self.n_in, int(width), int(seed), lo_p, hi_p, float(y_scale),
+                                     C.byref(h)))
+        self.h = h
+        self.n_params = int(lib.pmc_mlp_num_params(h))
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib.pmc_mlp_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        self.ctx.check(lib.pmc_mlp_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        self.ctx.check(lib.pmc_mlp_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def train_epoch(self, x, y, batch=4096, lr_max=1e-3, lr_min=1e-5, total_steps=1, beta1=0.9, beta2=0.999,
+                    eps=1e-8):
+        o = TrainOpts(int(batch), float(lr_max), float(lr_min), int(total_steps), float(beta1), float(beta2),
+                      float(eps))
+        loss = C.c_double()
+        self.ctx.check(lib.pmc_mlp_train_epoch(self.h, _ptr(x), _ptr(y), int(y.numel()), C.byref(o),
+                                               C.byref(loss)))
+        return loss.value
+
+    def infer(self, x, y):
+        self.ctx.check(lib.pmc_mlp_infer(self.h, _ptr(x), _ptr(y), int(y.numel())))
+
+    def loss_grad(self, x, y):
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = C.c_double()
+        self.ctx.check(lib.pmc_mlp_loss_grad(self.h, _ptr(x), _ptr(y), int(y.numel()), C.byref(loss),
+                                             g.ctypes.data_as(C.POINTER(C.c_float))))
+        return loss.value, g
+
+
 def eval_paths(payoff: Payoff, paths, tenv=(), params=(), *, spot, vol, corr=None, rate=0.03,
                years_per_day=1.0, **opts):
     g, keep = make_model(spot, vol, corr, rate, years_per_day)

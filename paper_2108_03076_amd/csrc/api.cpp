@@ -18,6 +18,7 @@
 
 #include "../../include/pmc.h"
 #include "codegen.h"
+#include "ctx.h"
 #include "ilc.h"
 #include "kernels.h"
 
@@ -77,7 +78,9 @@ struct pmc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  DevBuf blob, partial, result, bad, queue, paths, sobol, chol;
+  DevBuf blob, partial, result, bad, queue, paths, sobol, chol, sobol_hi;
+  int sobol_hi_rows = 0, sobol_hi_dims = 0, sobol_hi_bits = 0;
+  std::vector<uint8_t> last_upload;   // bytes the blob holds (skip identical uploads)
   HostPinned staging;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evk[3] = {nullptr, nullptr, nullptr};   // around the generation and MC kernels
@@ -111,6 +114,12 @@ static int fail(pmc_ctx* c, int st, const std::string& m) {
       return fail(ctx, e_ == hipErrorOutOfMemory ? PMC_E_OOM : PMC_E_HIP,            \
                   std::string(#expr) + ": " + hipGetErrorString(e_));                \
   } while (0)
+
+namespace pmc {
+hipStream_t ctx_stream(const pmc_ctx* c) { return c->stream; }
+int ctx_device(const pmc_ctx* c) { return c->device; }
+int ctx_fail(pmc_ctx* c, int status, const std::string& msg) { return fail(c, status, msg); }
+}  // namespace pmc
 
 extern "C" const char* pmc_version(void) { return "pmc 1.0 (gfx950)"; }
 
@@ -222,6 +231,7 @@ extern "C" int pmc_cholesky(pmc_ctx* c, const double* a, int n, int m, double* l
   HIP_TRY(c, hipSetDevice(c->device));
   size_t bytes = (size_t)n * m * m * sizeof(double);
   HIP_TRY(c, c->blob.ensure(bytes));
+  c->last_upload.clear();   // the blob is reused for the input below
   HIP_TRY(c, c->chol.ensure(bytes));
   HIP_TRY(c, c->bad.ensure(sizeof(int)));
   const int big = 0x7fffffff;
@@ -373,6 +383,26 @@ int ensure_sobol(pmc_ctx* c, int dims) {
   return PMC_OK;
 }
 
+// Per-wave high-part table of the Sobol points 0 .. n-1 (kept while the
+// shape is unchanged; limited to 64 MB).
+int ensure_sobol_hi(pmc_ctx* c, uint64_t n, int dims, int bits, const uint32_t** out) {
+  *out = nullptr;
+  const uint64_t rows = (n + 63) / 64;
+  const uint64_t bytes = rows * (uint64_t)dims * 4u;
+  if (bytes > (64ull << 20)) return PMC_OK;
+  if (c->sobol_hi_rows >= (int)rows && c->sobol_hi_dims == dims && c->sobol_hi_bits == bits) {
+    *out = (const uint32_t*)c->sobol_hi.p;
+    return PMC_OK;
+  }
+  HIP_TRY(c, c->sobol_hi.ensure((size_t)bytes));
+  HIP_TRY(c, launch_sobol_hi((const uint32_t*)c->sobol.p, (uint32_t*)c->sobol_hi.p, (int)rows, dims, bits, c->stream));
+  c->sobol_hi_rows = (int)rows;
+  c->sobol_hi_dims = dims;
+  c->sobol_hi_bits = bits;
+  *out = (const uint32_t*)c->sobol_hi.p;
+  return PMC_OK;
+}
+
 int sobol_bits(uint64_t n) {
   int b = 1;
   while (b < 32 && ((n - 1) >> b) != 0) ++b;
@@ -382,7 +412,7 @@ int sobol_bits(uint64_t n) {
 // Uploads the tables and fills the launch arguments (except work items).
 template <typename T>
 int upload(pmc_ctx* c, const Program& P, const Tables<T>& tb, const pmc_opts& o, McLaunch& L,
-           const std::vector<int2>* work) {
+           const std::vector<int>* order) {
   Pack pk;
   std::vector<T> consts(P.consts.size());
   for (size_t i = 0; i < consts.size(); ++i) consts[i] = (T)P.consts[i];
@@ -392,14 +422,18 @@ int upload(pmc_ctx* c, const Program& P, const Tables<T>& tb, const pmc_opts& o,
   const size_t o_itab = pk.add(tb.itab.data(), tb.itab.size() * sizeof(int32_t));
   const size_t o_rtab = pk.add(tb.rtab.data(), tb.rtab.size() * sizeof(T));
   const size_t o_corr = pk.add(tb.corr.data(), tb.corr.size() * sizeof(double));
-  size_t o_work = 0;
-  if (work) o_work = pk.add(work->data(), work->size() * sizeof(int2));
+  size_t o_order = 0;
+  if (order) o_order = pk.add(order->data(), order->size() * sizeof(int));
+  void* old_blob = c->blob.p;
   HIP_TRY(c, c->blob.ensure(pk.bytes.size()));
-  HIP_TRY(c, c->staging.ensure(pk.bytes.size()));
-  // the previous launch may still read the staging buffer's last copy
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::memcpy(c->staging.p, pk.bytes.data(), pk.bytes.size());
-  HIP_TRY(c, hipMemcpyAsync(c->blob.p, c->staging.p, pk.bytes.size(), hipMemcpyHostToDevice, c->stream));
+  if (c->blob.p != old_blob || c->last_upload != pk.bytes) {
+    HIP_TRY(c, c->staging.ensure(pk.bytes.size()));
+    // the previous call may still read the staging buffer's last copy
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::memcpy(c->staging.p, pk.bytes.data(), pk.bytes.size());
+    HIP_TRY(c, hipMemcpyAsync(c->blob.p, c->staging.p, pk.bytes.size(), hipMemcpyHostToDevice, c->stream));
+    c->last_upload.swap(pk.bytes);
+  }
   HIP_TRY(c, c->chol.ensure(std::max<size_t>(tb.corr.size(), 1) * sizeof(double)));
   uint8_t* b = (uint8_t*)c->blob.p;
   L = McLaunch{};
@@ -409,7 +443,7 @@ int upload(pmc_ctx* c, const Program& P, const Tables<T>& tb, const pmc_opts& o,
   L.itab = (const int32_t*)(b + o_itab);
   L.rtab = b + o_rtab;
   L.chol = (const double*)c->chol.p;
-  L.work = work ? (const int2*)(b + o_work) : nullptr;
+  L.order = order ? (const int*)(b + o_order) : nullptr;
   L.k0 = (uint32_t)(o.seed & 0xFFFFFFFFull);
   L.k1 = (uint32_t)(o.seed >> 32);
   L.n_assets = (int)P.assets.size();
@@ -420,25 +454,34 @@ int upload(pmc_ctx* c, const Program& P, const Tables<T>& tb, const pmc_opts& o,
     if (st != PMC_OK) return st;
     L.sobol = (const uint32_t*)c->sobol.p;
     L.sobol_bits = sobol_bits(o.n_paths);
+    const int dims = std::max(1, tb.max_dims);
+    st = ensure_sobol_hi(c, o.n_paths, dims, L.sobol_bits, &L.sobol_hi);
+    if (st != PMC_OK) return st;
+    L.sobol_dims = dims;
   }
   L.chol_in = (const double*)(b + o_corr);
   return PMC_OK;
 }
 
+// The result buffer holds n_inst (sum, sum of squares) pairs followed by the
+// Cholesky status word, so one copy returns both.
+int* status_word(pmc_ctx* c, int n_inst) { return (int*)((char*)c->result.p + (size_t)n_inst * sizeof(double2)); }
+
 int factor(pmc_ctx* c, const McLaunch& L, int n_inst, int A) {
-  HIP_TRY(c, c->bad.ensure(sizeof(int)));
-  HIP_TRY(c, launch_fill_u32((uint32_t*)c->bad.p, 0x7fffffffu, 1, c->stream));
-  HIP_TRY(c, launch_cholesky(L.chol_in, (double*)c->chol.p, (int*)c->bad.p, n_inst, A, c->stream));
+  HIP_TRY(c, c->result.ensure((size_t)(n_inst + 1) * sizeof(double2)));
+  int* bad = status_word(c, n_inst);
+  HIP_TRY(c, launch_fill_u32((uint32_t*)bad, 0x7fffffffu, 1, c->stream));
+  HIP_TRY(c, launch_cholesky(L.chol_in, (double*)c->chol.p, bad, n_inst, A, c->stream));
   return PMC_OK;
 }
 
 int finish(pmc_ctx* c, int n_inst, const std::vector<uint64_t>& n_paths, const std::vector<int>& n_slots,
            int mode_used, double ms, pmc_result* out, double gen_ms = 0.0, double eval_ms = 0.0) {
-  std::vector<double2> res(n_inst);
-  int bad = 0;
-  HIP_TRY(c, hipMemcpyAsync(res.data(), c->result.p, n_inst * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(&bad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  std::vector<double2> res(n_inst + 1);
+  HIP_TRY(c, hipMemcpyAsync(res.data(), c->result.p, (n_inst + 1) * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int bad = 0;
+  std::memcpy(&bad, &res[n_inst], sizeof(int));
   if (bad != 0x7fffffff) return fail(c, PMC_E_NOT_PD, "correlation matrix of instance " + std::to_string(bad) + " is not positive definite");
   for (int i = 0; i < n_inst; ++i) {
     const double N = (double)n_paths[i];
@@ -511,7 +554,7 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   st = upload<T>(c, P, tb, *o, L, nullptr);
   if (st != PMC_OK) return st;
   HIP_TRY(c, c->partial.ensure((size_t)tiles * sizeof(double2)));
-  HIP_TRY(c, c->result.ensure(sizeof(double2)));
+  HIP_TRY(c, c->result.ensure(2 * sizeof(double2)));
   L.partial = (double2*)c->partial.p;
   L.n_work = (int)tiles;
   L.payoff_out = o->payoffs_dev;
@@ -594,7 +637,7 @@ int gen_paths(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const pmc_gb
   if (st != PMC_OK) return st;
   HIP_TRY(c, launch_pathgen(sizeof(T) == 8 ? 1 : 0, o->rng, L, paths, words, normals, (uint32_t)o->n_paths, 256, c->stream));
   int bad = 0;
-  HIP_TRY(c, hipMemcpyAsync(&bad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&bad, status_word(c, 1), sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (bad != 0x7fffffff) return fail(c, PMC_E_NOT_PD, "correlation matrix is not positive definite");
   return PMC_OK;
@@ -648,36 +691,36 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
     st = build_instance<T>(c, P, *m, *o, in, i, tb);
     if (st != PMC_OK) return st;
   }
-  // work items: (instance, tile), instances with the most slots first
+  // work items (instance, tile), instances with the most slots first; the
+  // item list is implicit: item i is tile i % tiles of instance order[i / tiles]
   const uint64_t N = o->n_paths;
   const uint32_t tile_paths = (uint32_t)block * (uint32_t)ppt;
   const uint32_t tiles = (uint32_t)((N + tile_paths - 1) / tile_paths);
+  const size_t n_work = (size_t)I * tiles;
+  if (n_work > (1u << 26))
+    return fail(c, PMC_E_UNSUPPORTED, "batch needs more than 2^26 work items; raise paths per thread");
   std::vector<int> order(I);
   for (int i = 0; i < I; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tb.n_slots[x] > tb.n_slots[y]; });
-  std::vector<int2> work;
-  work.reserve((size_t)I * tiles);
-  for (int i : order)
-    for (uint32_t t = 0; t < tiles; ++t) work.push_back(make_int2(i, (int)t));
   for (int i = 0; i < I; ++i) {
     tb.desc[i].n_tiles = tiles;
     tb.desc[i].first_item = (int32_t)((size_t)i * tiles);
   }
   McLaunch L;
-  int st = upload<T>(c, P, tb, *o, L, &work);
+  int st = upload<T>(c, P, tb, *o, L, &order);
   if (st != PMC_OK) return st;
-  HIP_TRY(c, c->partial.ensure(work.size() * sizeof(double2)));
-  HIP_TRY(c, c->result.ensure((size_t)I * sizeof(double2)));
+  L.tiles = (int)tiles;
+  HIP_TRY(c, c->partial.ensure(n_work * sizeof(double2)));
+  HIP_TRY(c, c->result.ensure((size_t)(I + 1) * sizeof(double2)));
   HIP_TRY(c, c->queue.ensure(sizeof(uint32_t)));
-  HIP_TRY(c, c->bad.ensure(sizeof(int)));
   L.partial = (double2*)c->partial.p;
-  L.n_work = (int)work.size();
+  L.n_work = (int)n_work;
   L.queue = (uint32_t*)c->queue.p;
   L.ppt = ppt;
   L.payoff_out = nullptr;
   bp.L = L;
   const int occ = mc_occupancy(sizeof(T) == 8 ? 1 : 0, o->rng, A, P.n_regs, block);
-  bp.grid = std::max(1, std::min<int>((int)work.size(), c->n_cu * occ));
+  bp.grid = std::max(1, std::min<int>((int)n_work, c->n_cu * occ));
   bp.block = block; bp.ppt = ppt; bp.n_inst = I;
   bp.n_paths.assign(I, N);
   bp.n_slots = tb.n_slots;
@@ -704,7 +747,8 @@ int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_op
   std::ostringstream key;
   key << p->hash << ':' << bp.n_inst << ':' << bp.grid << ':' << bp.block << ':' << bp.ppt << ':' << bp.L.n_work
       << ':' << prec << ':' << o->rng << ':' << o->engine << ':' << c->blob.p << ':' << c->partial.p << ':' << c->result.p << ':'
-      << c->chol.p << ':' << c->sobol.p << ':' << (const void*)bp.L.desc << ':' << (const void*)bp.L.work;
+      << c->chol.p << ':' << c->sobol.p << ':' << (const void*)bp.L.sobol_hi << ':' << (const void*)bp.L.desc << ':'
+      << (const void*)bp.L.order;
   if (c->graph.key != key.str()) {
     if (c->graph.exec) { (void)hipGraphExecDestroy(c->graph.exec); c->graph.exec = nullptr; }
     c->graph.key.clear();
@@ -772,7 +816,16 @@ extern "C" int pmc_price_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch*
   HIP_TRY(c, hipSetDevice(c->device));
   int block = o->block ? o->block : 256, ppt = 1;
   auto it = c->tuned.find(tune_key(c, p, b, o));
-  if (it != c->tuned.end() && !o->block) { block = it->second.first; ppt = it->second.second; }
+  if (it != c->tuned.end() && !o->block) {
+    block = it->second.first;
+    ppt = it->second.second;
+  } else {
+    // untuned: enough paths per thread to keep the item count (and the
+    // partial-sum buffer) below 2^22
+    while (ppt < 1024 && (uint64_t)b->n_inst * ((o->n_paths + (uint64_t)block * ppt - 1) / ((uint64_t)block * ppt)) >
+                             (1ull << 22))
+      ppt *= 2;
+  }
   BatchPlan bp;
   st = o->precision == PMC_FP64 ? batch_prepare<double>(c, p, b, m, o, block, ppt, bp)
                                 : batch_prepare<float>(c, p, b, m, o, block, ppt, bp);
@@ -810,6 +863,7 @@ extern "C" int pmc_autotune_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_bat
   int bb = 256, bpp = 1;
   for (int bl : blocks)
     for (int pp : ppts) {
+      if ((uint64_t)b->n_inst * ((o->n_paths + (uint64_t)bl * pp - 1) / ((uint64_t)bl * pp)) > (1ull << 24)) continue;
       BatchPlan bp;
       st = o->precision == PMC_FP64 ? batch_prepare<double>(c, p, b, m, o, bl, pp, bp)
                                     : batch_prepare<float>(c, p, b, m, o, bl, pp, bp);

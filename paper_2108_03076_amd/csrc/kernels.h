@@ -19,7 +19,11 @@ struct McLaunch {
   const double* chol_in;      // packed FP64 correlation matrices (factored on device)
   const uint32_t* sobol;      // direction numbers [dim][32]
   int sobol_bits;             // bits of the largest path index
-  const int2* work;           // (instance, tile) items, or nullptr: item = (0, block)
+  const uint32_t* sobol_hi;   // per-wave high-part table [path/64][dim], or nullptr
+  int sobol_dims;             // row length of sobol_hi
+  const int* order;           // instance order (item i -> order[i / tiles], tile i % tiles),
+                              // or nullptr: item = (instance 0, tile = block)
+  int tiles;                  // tiles per instance
   int n_work;
   uint32_t* queue;            // work counter (persistent launch) or nullptr
   double2* partial;           // per item: (sum, sum of squares)
@@ -41,6 +45,8 @@ hipError_t launch_reduce(const double2* partial, const InstDesc* desc, int n_ins
                          hipStream_t s);
 hipError_t launch_cholesky(const double* a, double* l, int* bad, int n, int m, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s);
+// hi[h][d] = XOR of sobol[d][b] over the set bits b >= 6 of gray(64 h).
+hipError_t launch_sobol_hi(const uint32_t* sobol, uint32_t* hi, int n_rows, int dims, int bits, hipStream_t s);
 // Largest resident blocks per CU for the persistent MC kernel.
 int mc_occupancy(int precision, int rng, int n_assets, int n_regs, int block);
 

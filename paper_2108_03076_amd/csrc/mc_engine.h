@@ -126,7 +126,10 @@ struct Args {
   const double* chol;
   const uint32_t* sobol;
   int sobol_bits;
-  const int2* work;
+  const uint32_t* sobol_hi;   // [path / 64][dim]: Sobol bits 6.. of each wave's points, or null
+  int sobol_dims;
+  const int* order;      // instances in processing order (longest first), or null
+  int tiles;             // work items (path tiles) per instance
   int n_work;
   uint32_t* queue;
   double2* partial;
@@ -186,8 +189,10 @@ struct GenSource {
   uint32_t buf[4];
   uint32_t path, gray;
   uint32_t k0, k1, inst;
-  int n_slots, sobol_bits;
+  int n_slots, sobol_bits, sobol_dims;
   kptr<uint32_t> sobol;
+  kptr<uint32_t> sobol_hi;   // this wave's row of the high-part table
+  uint32_t gmask[6];         // -(bit b of the point's Gray code), b < 6
   kptr<T> slotc;
   kptr<T> spotp;
   Model<T, A> M;
@@ -196,6 +201,17 @@ struct GenSource {
     path = p; gray = p ^ (p >> 1);
     k0 = g.k0; k1 = g.k1; inst = d.instance;
     n_slots = d.n_slots; sobol_bits = g.sobol_bits; sobol = K(g.sobol);
+    sobol_dims = g.sobol_dims;
+    sobol_hi = nullptr;
+    if (RNG == 1 && g.sobol_hi) {
+      // Points 64h .. 64h+63 of one wave share Gray-code bits 6 and up
+      // (gray(p) >> 6 = gray(p >> 6)); their XOR of direction numbers is a
+      // per-wave table entry, and only bits 0..5 remain per lane.
+      const uint32_t h = (uint32_t)uni((int)(p >> 6));
+      sobol_hi = K(g.sobol_hi) + (size_t)h * (size_t)sobol_dims;
+#pragma unroll
+      for (int b = 0; b < 6; ++b) gmask[b] = 0u - ((gray >> b) & 1u);
+    }
     M.load(g, d);
     slotc = K(g.rtab) + d.slot_off;
     spotp = K(g.rtab) + d.model_off + 2 * A;
@@ -215,6 +231,12 @@ struct GenSource {
       return j == 0 ? buf[0] : j == 1 ? buf[1] : j == 2 ? buf[2] : buf[3];
     } else {
       kptr<uint32_t> v = sobol + (size_t)w * 32u;
+      if (sobol_hi) {
+        uint32_t acc = sobol_hi[w];
+#pragma unroll
+        for (int b = 0; b < 6; ++b) acc ^= v[b] & gmask[b];
+        return acc;
+      }
       uint32_t acc = 0;
       for (int b = 0; b < sobol_bits; ++b) acc ^= v[b] & (0u - ((gray >> b) & 1u));
       return acc;
@@ -466,11 +488,9 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
       __syncthreads();
     }
     if (item >= g.n_work) break;
+    // item -> (instance, tile): consecutive items cover one instance's tiles
     int2 wi = make_int2(0, item);
-    if (g.work) {
-      kptr<int> wp = K(reinterpret_cast<const int*>(g.work)) + 2 * item;
-      wi = make_int2(wp[0], wp[1]);
-    }
+    if (g.order) wi = make_int2(K(g.order)[item / g.tiles], item % g.tiles);
     const InstDesc D = load_desc(g.desc, wi.x);
     double s = 0.0, ss = 0.0;
     for (int r = 0; r < g.ppt; ++r) {

@@ -24,9 +24,10 @@ Args<T> typed(const McLaunch& a) {
   Args<T> g;
   g.code = a.code; g.consts = (const T*)a.consts; g.desc = a.desc; g.itab = a.itab;
   g.rtab = (const T*)a.rtab; g.chol = a.chol; g.sobol = a.sobol; g.sobol_bits = a.sobol_bits;
-  g.work = a.work; g.n_work = a.n_work; g.queue = a.queue; g.partial = a.partial;
+  g.order = a.order; g.tiles = a.tiles; g.n_work = a.n_work; g.queue = a.queue; g.partial = a.partial;
   g.payoff_out = (T*)a.payoff_out; g.paths = (const T*)a.paths; g.k0 = a.k0; g.k1 = a.k1;
   g.ppt = a.ppt; g.n_assets = a.n_assets;
+  g.sobol_hi = a.sobol_hi; g.sobol_dims = a.sobol_dims;
   return g;
 }
 
@@ -74,6 +75,17 @@ __global__ void k_cholesky(const double* a, double* l, int* bad, int n, int m) {
     }
   }
   if (!ok) atomicMin(bad, i);
+}
+
+__global__ void k_sobol_hi(const uint32_t* v, uint32_t* hi, int n_rows, int dims, int bits) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rows * dims) return;
+  const uint32_t h = (uint32_t)(i / dims), d = (uint32_t)(i % dims);
+  const uint32_t gh = h ^ (h >> 1);   // Gray-code bits 6.. of points 64h .. 64h+63
+  uint32_t acc = 0;
+  for (int b = 6; b < bits; ++b)
+    if ((gh >> (b - 6)) & 1u) acc ^= v[d * 32u + b];
+  hi[i] = acc;
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int n) {
@@ -173,6 +185,12 @@ hipError_t launch_reduce(const double2* partial, const InstDesc* desc, int n_ins
 
 hipError_t launch_cholesky(const double* a, double* l, int* bad, int n, int m, hipStream_t s) {
   hipLaunchKernelGGL(k_cholesky, dim3((n + 255) / 256), dim3(256), 0, s, a, l, bad, n, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_sobol_hi(const uint32_t* sobol, uint32_t* hi, int n_rows, int dims, int bits, hipStream_t s) {
+  const int n = n_rows * dims;
+  hipLaunchKernelGGL(k_sobol_hi, dim3((n + 255) / 256), dim3(256), 0, s, sobol, hi, n_rows, dims, bits);
   return hipGetLastError();
 }
 

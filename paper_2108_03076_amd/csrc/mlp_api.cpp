@@ -1,0 +1,327 @@
+// C ABI of the learned surrogate: an MLP n_in -> W -> W -> W -> 1 with GELU,
+// BF16 weights and activations, FP32 accumulation on the matrix cores, FP32
+// master weights and Adam.  Parameters are kept flat on the device in the
+// order W1 b1 W2 b2 W3 b3 W4 b4 (each W row-major [out][in]).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/pmc.h"
+#include "ctx.h"
+#include "mlp_kernels.h"
+
+using namespace pmc;
+
+namespace {
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+  ~Buf() { if (p) (void)hipFree(p); }
+  hipError_t ensure(size_t n) {
+    if (n <= cap) return hipSuccess;
+    if (p) { (void)hipFree(p); p = nullptr; cap = 0; }
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipSuccess) cap = n;
+    return e;
+  }
+  template <typename T> T* as() const { return (T*)p; }
+};
+
+constexpr int kSplits = 16;   // split-K factor of the weight-gradient GEMMs
+
+}  // namespace
+
+struct pmc_mlp {
+  pmc_ctx* ctx = nullptr;
+  int n_in = 8, width = 256;
+  double y_scale = 100.0;
+  int64_t n_params = 0;
+  int64_t step = 0;
+  // flat parameter offsets
+  int64_t oW[4], ob[4];
+  int out_[4], in_[4], outp[4], inp[4];
+  Buf master, m, v, grad, lohi;
+  Buf W[4], Wt[4];
+  // batch-sized work buffers
+  int B = 0;
+  Buf X, Xt, Z[3], H[3], Ht[3], Y, dZ4, dZ4t, dZ[3], dZt[3], part_loss, loss_acc, partial;
+};
+
+#define MLP_TRY(m, expr)                                                                           \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      return ctx_fail((m)->ctx, e_ == hipErrorOutOfMemory ? PMC_E_OOM : PMC_E_HIP,                 \
+                      std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+  } while (0)
+
+namespace {
+
+int pack_all(pmc_mlp* M) {
+  hipStream_t s = ctx_stream(M->ctx);
+  for (int l = 0; l < 4; ++l)
+    MLP_TRY(M, mlp_pack(M->master.as<float>() + M->oW[l], M->out_[l], M->in_[l], M->outp[l], M->inp[l],
+                        M->W[l].as<__bf16>(), M->Wt[l].as<__bf16>(), s));
+  return PMC_OK;
+}
+
+int ensure_batch(pmc_mlp* M, int B) {
+  if (B <= M->B) return PMC_OK;
+  const int W = M->width;
+  const size_t b = (size_t)B;
+  MLP_TRY(M, M->X.ensure(b * 16 * 2));
+  MLP_TRY(M, M->Xt.ensure(b * 32 * 2));
+  for (int l = 0; l < 3; ++l) {
+    MLP_TRY(M, M->Z[l].ensure(b * W * 4));
+    MLP_TRY(M, M->H[l].ensure(b * W * 2));
+    MLP_TRY(M, M->Ht[l].ensure(b * W * 2));
+    MLP_TRY(M, M->dZ[l].ensure(b * W * 2));
+    MLP_TRY(M, M->dZt[l].ensure(b * W * 2));
+  }
+  MLP_TRY(M, M->Y.ensure(b * 4));
+  MLP_TRY(M, M->dZ4.ensure(b * 32 * 2));
+  MLP_TRY(M, M->dZ4t.ensure(b * 32 * 2));
+  MLP_TRY(M, M->part_loss.ensure(((b + 255) / 256) * 8));
+  MLP_TRY(M, M->loss_acc.ensure(8));
+  MLP_TRY(M, M->partial.ensure((size_t)kSplits * W * W * 4));
+  M->B = B;
+  return PMC_OK;
+}
+
+// Forward pass over B rows (n real) of raw inputs x; saves what backward needs
+// when train is set.
+int forward(pmc_mlp* M, const float* x, int n, int B, bool train) {
+  hipStream_t s = ctx_stream(M->ctx);
+  const int W = M->width;
+  const float* w = M->master.as<float>();
+  MLP_TRY(M, mlp_scale_inputs(x, n, M->n_in, M->lohi.as<float>(), M->lohi.as<float>() + 32, B,
+                              M->X.as<__bf16>(), M->Xt.as<__bf16>(), s));
+  const __bf16* in = M->X.as<__bf16>();
+  int ld = 16;
+  for (int l = 0; l < 3; ++l) {
+    if (train)
+      MLP_TRY(M, mlp_gemm_hidden(B, W, M->inp[l], in, ld, M->W[l].as<__bf16>(), M->inp[l], w + M->ob[l],
+                                 M->Z[l].as<float>(), M->H[l].as<__bf16>(), M->Ht[l].as<__bf16>(), s));
+    else
+      MLP_TRY(M, mlp_gemm_hidden_infer(B, W, M->inp[l], in, ld, M->W[l].as<__bf16>(), M->inp[l], w + M->ob[l],
+                                       M->H[l].as<__bf16>(), s));
+    in = M->H[l].as<__bf16>();
+    ld = W;
+  }
+  MLP_TRY(M, mlp_gemm_out(B, 32, W, in, W, M->W[3].as<__bf16>(), W, w + M->ob[3], M->Y.as<float>(),
+                          train ? 1.0f : (float)M->y_scale, s));
+  return PMC_OK;
+}
+
+// Loss and gradients (into M->grad) of mean((yhat - y/y_scale)^2) over n
+// rows; adds the batch's sum of squared errors to loss_acc.
+int backward(pmc_mlp* M, const float* y, int n, int B) {
+  hipStream_t s = ctx_stream(M->ctx);
+  const int W = M->width;
+  float* g = M->grad.as<float>();
+  MLP_TRY(M, mlp_loss(M->Y.as<float>(), y, n, B, (float)(1.0 / M->y_scale), 2.0f / (float)n,
+                      M->dZ4.as<__bf16>(), M->dZ4t.as<__bf16>(), M->part_loss.as<double>(),
+                      M->loss_acc.as<double>(), s));
+  float* part = M->partial.as<float>();
+  // layer 4: dW4 = dZ4^T H3, db4, dZ3 = (dZ4 W4) * gelu'(Z3)
+  MLP_TRY(M, mlp_gemm_f32(32, W, B, M->dZ4t.as<__bf16>(), B, M->Ht[2].as<__bf16>(), B, kSplits, part, W, s));
+  MLP_TRY(M, mlp_reduce_splits(part, kSplits, (size_t)32 * W, W, 1, W, g + M->oW[3], s));
+  MLP_TRY(M, mlp_rowsum(M->dZ4t.as<__bf16>(), B, 1, g + M->ob[3], s));
+  MLP_TRY(M, mlp_gemm_back_hidden(B, W, 32, M->dZ4.as<__bf16>(), 32, M->Wt[3].as<__bf16>(), 32,
+                                  M->Z[2].as<float>(), M->dZ[2].as<__bf16>(), M->dZt[2].as<__bf16>(), s));
+  // layers 3 and 2
+  for (int l = 2; l >= 1; --l) {
+    MLP_TRY(M, mlp_gemm_f32(W, W, B, M->dZt[l].as<__bf16>(), B, M->Ht[l - 1].as<__bf16>(), B, kSplits, part, W, s));
+    MLP_TRY(M, mlp_reduce_splits(part, kSplits, (size_t)W * W, W, W, W, g + M->oW[l], s));
+    MLP_TRY(M, mlp_rowsum(M->dZt[l].as<__bf16>(), B, W, g + M->ob[l], s));
+    MLP_TRY(M, mlp_gemm_back_hidden(B, W, W, M->dZ[l].as<__bf16>(), W, M->Wt[l].as<__bf16>(), W,
+                                    M->Z[l - 1].as<float>(), M->dZ[l - 1].as<__bf16>(),
+                                    M->dZt[l - 1].as<__bf16>(), s));
+  }
+  // layer 1: dW1 = dZ1^T X (X^T has 32 padded rows), db1
+  MLP_TRY(M, mlp_gemm_f32(W, 32, B, M->dZt[0].as<__bf16>(), B, M->Xt.as<__bf16>(), B, kSplits, part, 32, s));
+  MLP_TRY(M, mlp_reduce_splits(part, kSplits, (size_t)W * 32, 32, W, M->n_in, g + M->oW[0], s));
+  MLP_TRY(M, mlp_rowsum(M->dZt[0].as<__bf16>(), B, W, g + M->ob[0], s));
+  return PMC_OK;
+}
+
+uint64_t splitmix(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" int pmc_mlp_create(pmc_ctx* ctx, int n_in, int width, uint64_t seed, const double* in_lo,
+                              const double* in_hi, double y_scale, pmc_mlp** out) {
+  if (!ctx || !out || !in_lo || !in_hi) return PMC_E_ARG;
+  if (n_in < 1 || n_in > 16 || width < 32 || width % 32 || width > 1024 || !(y_scale > 0))
+    return ctx_fail(ctx, PMC_E_UNSUPPORTED, "surrogate needs 1 <= n_in <= 16 and width a multiple of 32 up to 1024");
+  for (int i = 0; i < n_in; ++i)
+    if (!std::isfinite(in_lo[i]) || !std::isfinite(in_hi[i]) || !(in_hi[i] > in_lo[i]))
+      return ctx_fail(ctx, PMC_E_ARG, "input box must be finite with hi > lo");
+  auto M = std::make_unique<pmc_mlp>();
+  M->ctx = ctx;
+  M->n_in = n_in;
+  M->width = width;
+  M->y_scale = y_scale;
+  const int W = width;
+  const int outs[4] = {W, W, W, 1}, ins[4] = {n_in, W, W, W};
+  int64_t off = 0;
+  for (int l = 0; l < 4; ++l) {
+    M->out_[l] = outs[l];
+    M->in_[l] = ins[l];
+    M->outp[l] = l == 3 ? 32 : W;
+    M->inp[l] = l == 0 ? 16 : W;
+    M->oW[l] = off;
+    off += (int64_t)outs[l] * ins[l];
+    M->ob[l] = off;
+    off += outs[l];
+  }
+  M->n_params = off;
+  // PyTorch-style initialisation: U(-1/sqrt(in), 1/sqrt(in)) for W and b
+  std::vector<float> h((size_t)off);
+  uint64_t st = seed;
+  for (int l = 0; l < 4; ++l) {
+    const double a = 1.0 / std::sqrt((double)ins[l]);
+    for (int64_t i = M->oW[l]; i < M->ob[l] + outs[l]; ++i) {
+      const double u = (double)(splitmix(st) >> 11) * 0x1p-53;
+      h[i] = (float)((2.0 * u - 1.0) * a);
+    }
+  }
+  std::vector<float> lohi(64, 0.0f);
+  for (int i = 0; i < n_in; ++i) { lohi[i] = (float)in_lo[i]; lohi[32 + i] = (float)in_hi[i]; }
+  for (int i = n_in; i < 32; ++i) { lohi[i] = 0.0f; lohi[32 + i] = 1.0f; }
+  pmc_mlp* m = M.get();
+  hipStream_t s = ctx_stream(ctx);
+  MLP_TRY(m, hipSetDevice(ctx_device(ctx)));
+  const size_t pb = (size_t)off * 4;
+  MLP_TRY(m, m->master.ensure(pb));
+  MLP_TRY(m, m->m.ensure(pb));
+  MLP_TRY(m, m->v.ensure(pb));
+  MLP_TRY(m, m->grad.ensure(pb));
+  MLP_TRY(m, m->lohi.ensure(64 * 4));
+  for (int l = 0; l < 4; ++l) {
+    MLP_TRY(m, m->W[l].ensure((size_t)m->outp[l] * m->inp[l] * 2));
+    MLP_TRY(m, m->Wt[l].ensure((size_t)m->outp[l] * m->inp[l] * 2));
+  }
+  MLP_TRY(m, hipMemcpyAsync(m->master.p, h.data(), pb, hipMemcpyHostToDevice, s));
+  MLP_TRY(m, hipMemsetAsync(m->m.p, 0, pb, s));
+  MLP_TRY(m, hipMemsetAsync(m->v.p, 0, pb, s));
+  MLP_TRY(m, hipMemcpyAsync(m->lohi.p, lohi.data(), 64 * 4, hipMemcpyHostToDevice, s));
+  int rc = pack_all(m);
+  if (rc != PMC_OK) return rc;
+  MLP_TRY(m, hipStreamSynchronize(s));
+  *out = M.release();
+  return PMC_OK;
+}
+
+extern "C" void pmc_mlp_free(pmc_mlp* m) {
+  if (!m) return;
+  (void)hipStreamSynchronize(ctx_stream(m->ctx));
+  delete m;
+}
+
+extern "C" int64_t pmc_mlp_num_params(const pmc_mlp* m) { return m ? m->n_params : -1; }
+
+extern "C" int pmc_mlp_get_params(const pmc_mlp* m, float* out) {
+  if (!m || !out) return PMC_E_ARG;
+  pmc_mlp* M = const_cast<pmc_mlp*>(m);
+  MLP_TRY(M, hipMemcpyAsync(out, m->master.p, (size_t)m->n_params * 4, hipMemcpyDeviceToHost, ctx_stream(m->ctx)));
+  MLP_TRY(M, hipStreamSynchronize(ctx_stream(m->ctx)));
+  return PMC_OK;
+}
+
+extern "C" int pmc_mlp_set_params(pmc_mlp* m, const float* in) {
+  if (!m || !in) return PMC_E_ARG;
+  hipStream_t s = ctx_stream(m->ctx);
+  for (int64_t i = 0; i < m->n_params; ++i)
+    if (!std::isfinite(in[i])) return ctx_fail(m->ctx, PMC_E_ARG, "parameters must be finite");
+  MLP_TRY(m, hipMemcpyAsync(m->master.p, in, (size_t)m->n_params * 4, hipMemcpyHostToDevice, s));
+  MLP_TRY(m, hipMemsetAsync(m->m.p, 0, (size_t)m->n_params * 4, s));
+  MLP_TRY(m, hipMemsetAsync(m->v.p, 0, (size_t)m->n_params * 4, s));
+  m->step = 0;
+  int rc = pack_all(m);
+  if (rc != PMC_OK) return rc;
+  MLP_TRY(m, hipStreamSynchronize(s));
+  return PMC_OK;
+}
+
+extern "C" int pmc_mlp_infer(pmc_mlp* m, const float* x, float* y, int64_t n) {
+  if (!m || !x || !y || n < 1 || n > (1ll << 30)) return PMC_E_ARG;
+  hipStream_t s = ctx_stream(m->ctx);
+  const int chunk = 1 << 16;
+  for (int64_t o = 0; o < n; o += chunk) {
+    const int k = (int)std::min<int64_t>(chunk, n - o);
+    const int B = (k + 63) / 64 * 64;
+    int rc = ensure_batch(m, B);
+    if (rc != PMC_OK) return rc;
+    rc = forward(m, x + o * m->n_in, k, B, false);
+    if (rc != PMC_OK) return rc;
+    // the k real rows of the prices (network output times y_scale)
+    MLP_TRY(m, hipMemcpyAsync(y + o, m->Y.p, (size_t)k * sizeof(float), hipMemcpyDeviceToDevice, s));
+  }
+  MLP_TRY(m, hipStreamSynchronize(s));
+  return PMC_OK;
+}
+
+extern "C" int pmc_mlp_loss_grad(pmc_mlp* m, const float* x, const float* y, int64_t n, double* loss,
+                                 float* grad_out) {
+  if (!m || !x || !y || !loss || !grad_out || n < 1 || n > (1 << 16)) return PMC_E_ARG;
+  hipStream_t s = ctx_stream(m->ctx);
+  const int B = (int)((n + 63) / 64 * 64);
+  int rc = ensure_batch(m, B);
+  if (rc != PMC_OK) return rc;
+  MLP_TRY(m, hipMemsetAsync(m->loss_acc.p, 0, 8, s));
+  rc = forward(m, x, (int)n, B, true);
+  if (rc == PMC_OK) rc = backward(m, y, (int)n, B);
+  if (rc != PMC_OK) return rc;
+  double acc = 0;
+  MLP_TRY(m, hipMemcpyAsync(&acc, m->loss_acc.p, 8, hipMemcpyDeviceToHost, s));
+  MLP_TRY(m, hipMemcpyAsync(grad_out, m->grad.p, (size_t)m->n_params * 4, hipMemcpyDeviceToHost, s));
+  MLP_TRY(m, hipStreamSynchronize(s));
+  *loss = acc / (double)n;
+  return PMC_OK;
+}
+
+extern "C" int pmc_mlp_train_epoch(pmc_mlp* m, const float* x, const float* y, int64_t n, const pmc_train_opts* o,
+                                   double* mean_loss) {
+  if (!m || !x || !y || !o || n < 1) return PMC_E_ARG;
+  if (o->batch < 64 || o->batch % 64 || o->batch > (1 << 20) || o->total_steps < 1 || !(o->lr_max > 0) ||
+      !(o->lr_min >= 0) || !(o->beta1 >= 0 && o->beta1 < 1) || !(o->beta2 >= 0 && o->beta2 < 1) || !(o->eps > 0))
+    return ctx_fail(m->ctx, PMC_E_ARG, "bad training options (batch must be a multiple of 64)");
+  hipStream_t s = ctx_stream(m->ctx);
+  const int B = o->batch;
+  int rc = ensure_batch(m, B);
+  if (rc != PMC_OK) return rc;
+  MLP_TRY(m, hipMemsetAsync(m->loss_acc.p, 0, 8, s));
+  const int64_t steps = n / B;   // full batches only
+  if (steps < 1) return ctx_fail(m->ctx, PMC_E_ARG, "fewer samples than one batch");
+  for (int64_t k = 0; k < steps; ++k) {
+    rc = forward(m, x + k * B * m->n_in, B, B, true);
+    if (rc == PMC_OK) rc = backward(m, y + k * B, B, B);
+    if (rc != PMC_OK) return rc;
+    const double frac = std::min(1.0, (double)m->step / (double)o->total_steps);
+    const double lr = o->lr_min + 0.5 * (o->lr_max - o->lr_min) * (1.0 + std::cos(M_PI * frac));
+    m->step++;
+    const double c1 = 1.0 - std::pow(o->beta1, (double)m->step);
+    const double c2 = 1.0 - std::pow(o->beta2, (double)m->step);
+    MLP_TRY(m, mlp_adam(m->master.as<float>(), m->m.as<float>(), m->v.as<float>(), m->grad.as<float>(),
+                        (int)m->n_params, (float)lr, (float)o->beta1, (float)o->beta2, (float)o->eps, (float)c1,
+                        (float)c2, s));
+    rc = pack_all(m);
+    if (rc != PMC_OK) return rc;
+  }
+  double acc = 0;
+  MLP_TRY(m, hipMemcpyAsync(&acc, m->loss_acc.p, 8, hipMemcpyDeviceToHost, s));
+  MLP_TRY(m, hipStreamSynchronize(s));
+  if (mean_loss) *mean_loss = acc / (double)(steps * B);
+  return PMC_OK;
+}

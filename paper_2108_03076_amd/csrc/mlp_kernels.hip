@@ -1,0 +1,276 @@
+// Surrogate MLP kernels for gfx950: BF16 x BF16 -> FP32 GEMMs on the matrix
+// cores (v_mfma_f32_32x32x16_bf16) with fused epilogues (bias + GELU,
+// GELU'-scaled back-propagation, split-K weight gradients), plus the input
+// scaling, loss, bias-gradient, Adam and weight-packing kernels.
+#include <hip/hip_runtime.h>
+
+#include "mlp_kernels.h"
+
+namespace pmc {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
+__device__ __forceinline__ float from_bf16(__bf16 x) { return (float)x; }
+
+// GELU with the exact (erf) form and its derivative.
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+}
+
+// C = A * Bt^T with A [M x K] and Bt [N x K] row-major BF16 (K contiguous).
+// Block: 4 waves on a 64 x 64 output tile, each wave one 32 x 32 MFMA tile;
+// blockIdx.z splits K into chunks of k_chunk.  M, N multiples of 32, K and
+// k_chunk multiples of 16, lda/ldb multiples of 8 (16-byte rows).
+// MFMA operand layout (32x32x16): lane l supplies row l%32 of A (and of Bt)
+// at k = 8*(l/32) .. +7; accumulator element e of lane l is
+// C[8*(e/4) + 4*(l/32) + e%4][l%32].
+template <class Epi>
+__global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const __bf16* __restrict__ A, int lda,
+                                                 const __bf16* __restrict__ Bt, int ldb, int k_chunk, Epi epi) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
+  const int n0 = blockIdx.x * 64 + (w & 1) * 32;
+  if (m0 >= M || n0 >= N) return;
+  const int kbeg = blockIdx.z * k_chunk;
+  const int kend = min(K, kbeg + k_chunk);
+  const int r = lane & 31, kh = (lane >> 5) * 8;
+  const __bf16* pa = A + (size_t)(m0 + r) * lda + kh;
+  const __bf16* pb = Bt + (size_t)(n0 + r) * ldb + kh;
+  f32x16 acc;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
+  for (int k = kbeg; k < kend; k += 16) {
+    const bf16x8 a = *reinterpret_cast<const bf16x8*>(pa + k);
+    const bf16x8 b = *reinterpret_cast<const bf16x8*>(pb + k);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+  const int col = n0 + r;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int row = m0 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+    epi(row, col, acc[e], (int)blockIdx.z);
+  }
+}
+
+struct EpiF32 {          // C[z][row][col] (split-K partials or plain output)
+  float* c; int ldc; size_t zstride;
+  __device__ void operator()(int row, int col, float v, int z) const { c[z * zstride + (size_t)row * ldc + col] = v; }
+};
+
+struct EpiHidden {       // z = v + b; Z = z; H = gelu(z) (BF16) and its transpose
+  const float* bias; float* Z; int ldz; __bf16* H; int ldh; __bf16* Ht; int ldht;
+  __device__ void operator()(int row, int col, float v, int) const {
+    const float z = v + bias[col];
+    Z[(size_t)row * ldz + col] = z;
+    const __bf16 h = to_bf16(gelu(z));
+    H[(size_t)row * ldh + col] = h;
+    Ht[(size_t)col * ldht + row] = h;
+  }
+};
+
+struct EpiHiddenInfer {  // H = gelu(v + b) (BF16) only
+  const float* bias; __bf16* H; int ldh;
+  __device__ void operator()(int row, int col, float v, int) const {
+    H[(size_t)row * ldh + col] = to_bf16(gelu(v + bias[col]));
+  }
+};
+
+struct EpiOut {          // y = (v + b) * scale for output column 0
+  const float* bias; float* y; float scale;
+  __device__ void operator()(int row, int col, float v, int) const {
+    if (col == 0) y[row] = (v + bias[0]) * scale;
+  }
+};
+
+struct EpiBackHidden {   // dZ = dH * gelu'(Z) (BF16) and its transpose
+  const float* Z; int ldz; __bf16* dZ; int lddz; __bf16* dZt; int lddzt;
+  __device__ void operator()(int row, int col, float v, int) const {
+    const float g = v * gelu_grad(Z[(size_t)row * ldz + col]);
+    const __bf16 b = to_bf16(g);
+    dZ[(size_t)row * lddz + col] = b;
+    dZt[(size_t)col * lddzt + row] = b;
+  }
+};
+
+template <class Epi>
+hipError_t gemm(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb, int splits, Epi epi,
+                hipStream_t s) {
+  if (M % 32 || N % 32 || K % 16 || lda % 8 || ldb % 8 || splits < 1) return hipErrorInvalidValue;
+  int chunk = (K + splits - 1) / splits;
+  chunk = (chunk + 15) / 16 * 16;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, splits);
+  hipLaunchKernelGGL((k_gemm_nt<Epi>), grid, dim3(256), 0, s, M, N, K, A, lda, Bt, ldb, chunk, epi);
+  return hipGetLastError();
+}
+
+// x raw [n][n_in] -> X [B][16] BF16 scaled to [-1,1] (columns >= n_in zero)
+// and its transpose Xt [32][B] (rows >= n_in zero).  Rows >= n are zero.
+__global__ void k_scale_inputs(const float* __restrict__ x, int n, int n_in, const float* __restrict__ lo,
+                               const float* __restrict__ hi, int B, __bf16* X, __bf16* Xt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  for (int j = 0; j < 32; ++j) {
+    float v = 0.0f;
+    if (i < n && j < n_in) v = 2.0f * (x[(size_t)i * n_in + j] - lo[j]) / (hi[j] - lo[j]) - 1.0f;
+    const __bf16 b = to_bf16(v);
+    if (j < 16) X[(size_t)i * 16 + j] = b;
+    Xt[(size_t)j * B + i] = b;
+  }
+}
+
+// dy = 2 (yhat - t) / n_total for real rows (0 for padding), stored as the
+// first column of dZ4 [B][32] and first row of dZ4t [32][B]; per-block sums
+// of (yhat - t)^2 into part[block].
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ yhat, const float* __restrict__ t, int n,
+                                              int B, float inv_scale, float grad_scale, __bf16* dZ, __bf16* dZt,
+                                              double* part) {
+  __shared__ double red[256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double l = 0.0;
+  if (i < B) {
+    float d = 0.0f;
+    if (i < n) {
+      const float e = yhat[i] - t[i] * inv_scale;
+      l = (double)e * (double)e;
+      d = grad_scale * e;
+    }
+    const __bf16 b = to_bf16(d);
+    for (int j = 0; j < 32; ++j) {
+      dZ[(size_t)i * 32 + j] = j == 0 ? b : to_bf16(0.0f);
+      dZt[(size_t)j * B + i] = j == 0 ? b : to_bf16(0.0f);
+    }
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// out[0] += sum of part[0..n) in a fixed order (one thread).
+__global__ void k_sum_parts(const double* part, int n, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += part[i];
+  out[0] += s;
+}
+
+// g[row][col] (rows < rows_real, cols < cols_real, row-major ld cols_real)
+// = sum over z of partial[z][row][col] (ld ldp), fixed order.
+__global__ void k_reduce_splits(const float* __restrict__ partial, int splits, size_t zstride, int ldp,
+                                int rows_real, int cols_real, float* __restrict__ g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows_real * cols_real) return;
+  const int row = i / cols_real, col = i % cols_real;
+  float s = 0.0f;
+  for (int z = 0; z < splits; ++z) s += partial[z * zstride + (size_t)row * ldp + col];
+  g[i] = s;
+}
+
+// g[r] = sum over b of dZt[r][b] (BF16), one block per row, fixed order.
+__global__ __launch_bounds__(256) void k_rowsum(const __bf16* __restrict__ dZt, int B, int rows_real,
+                                                float* __restrict__ g) {
+  __shared__ float red[256];
+  const int r = blockIdx.x;
+  if (r >= rows_real) return;
+  float s = 0.0f;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) s += from_bf16(dZt[(size_t)r * B + b]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g[r] = red[0];
+}
+
+__global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, int n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// BF16 working copies of a layer's weights from the FP32 master [out][in]:
+// W [out_pad][in_pad] and Wt [in_pad][out_pad], zero padded.
+__global__ void k_pack(const float* __restrict__ master, int out, int in, int out_pad, int in_pad, __bf16* W,
+                       __bf16* Wt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= out_pad * in_pad) return;
+  const int o = i / in_pad, k = i % in_pad;
+  const float x = (o < out && k < in) ? master[(size_t)o * in + k] : 0.0f;
+  const __bf16 b = to_bf16(x);
+  W[(size_t)o * in_pad + k] = b;
+  Wt[(size_t)k * out_pad + o] = b;
+}
+
+}  // namespace
+
+hipError_t mlp_gemm_f32(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb, int splits,
+                        float* C, int ldc, hipStream_t s) {
+  return gemm(M, N, K, A, lda, Bt, ldb, splits, EpiF32{C, ldc, (size_t)M * ldc}, s);
+}
+hipError_t mlp_gemm_hidden(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb,
+                           const float* bias, float* Z, __bf16* H, __bf16* Ht, hipStream_t s) {
+  return gemm(M, N, K, A, lda, Bt, ldb, 1, EpiHidden{bias, Z, N, H, N, Ht, M}, s);
+}
+hipError_t mlp_gemm_hidden_infer(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb,
+                                 const float* bias, __bf16* H, hipStream_t s) {
+  return gemm(M, N, K, A, lda, Bt, ldb, 1, EpiHiddenInfer{bias, H, N}, s);
+}
+hipError_t mlp_gemm_out(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb, const float* bias,
+                        float* y, float scale, hipStream_t s) {
+  return gemm(M, N, K, A, lda, Bt, ldb, 1, EpiOut{bias, y, scale}, s);
+}
+hipError_t mlp_gemm_back_hidden(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb,
+                                const float* Z, __bf16* dZ, __bf16* dZt, hipStream_t s) {
+  return gemm(M, N, K, A, lda, Bt, ldb, 1, EpiBackHidden{Z, N, dZ, N, dZt, M}, s);
+}
+hipError_t mlp_scale_inputs(const float* x, int n, int n_in, const float* lo, const float* hi, int B, __bf16* X,
+                            __bf16* Xt, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_inputs, dim3((B + 255) / 256), dim3(256), 0, s, x, n, n_in, lo, hi, B, X, Xt);
+  return hipGetLastError();
+}
+hipError_t mlp_loss(const float* yhat, const float* t, int n, int B, float inv_scale, float grad_scale, __bf16* dZ,
+                    __bf16* dZt, double* part, double* acc, hipStream_t s) {
+  const int blocks = (B + 255) / 256;
+  hipLaunchKernelGGL(k_loss, dim3(blocks), dim3(256), 0, s, yhat, t, n, B, inv_scale, grad_scale, dZ, dZt, part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part, blocks, acc);
+  return hipGetLastError();
+}
+hipError_t mlp_reduce_splits(const float* partial, int splits, size_t zstride, int ldp, int rows, int cols,
+                             float* g, hipStream_t s) {
+  const int n = rows * cols;
+  hipLaunchKernelGGL(k_reduce_splits, dim3((n + 255) / 256), dim3(256), 0, s, partial, splits, zstride, ldp, rows,
+                     cols, g);
+  return hipGetLastError();
+}
+hipError_t mlp_rowsum(const __bf16* dZt, int B, int rows, float* g, hipStream_t s) {
+  hipLaunchKernelGGL(k_rowsum, dim3(rows), dim3(256), 0, s, dZt, B, rows, g);
+  return hipGetLastError();
+}
+hipError_t mlp_adam(float* w, float* m, float* v, const float* g, int n, float lr, float b1, float b2, float eps,
+                    float c1, float c2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+hipError_t mlp_pack(const float* master, int out, int in, int out_pad, int in_pad, __bf16* W, __bf16* Wt,
+                    hipStream_t s) {
+  const int n = out_pad * in_pad;
+  hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, s, master, out, in, out_pad, in_pad, W, Wt);
+  return hipGetLastError();
+}
+
+}  // namespace pmc

@@ -1,0 +1,110 @@
+"""GPU checks of the surrogate kernels against the FP64 reference, and a
+small end-to-end run of the surrogate workflow (labels from the batched
+Monte Carlo engine, training, Monte Carlo judge).
+
+Bars: BF16 weights and activations with FP32 accumulation against FP64:
+outputs within 3% of the output scale, loss within 3%, each layer's
+gradient within 5% relative norm error and cosine similarity >= 0.998."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import ctx
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+LO = np.array([70, 70, 70, 0.1, 0.1, 0.1, 0.0, 1.0])
+HI = np.array([130, 130, 130, 0.4, 0.4, 0.4, 0.9, 5.0])
+
+
+def _net(seed=0):
+    import paper_2108_03076_amd as P
+    sur = P.Surrogate(ctx(), LO, HI, y_scale=100.0, width=256, seed=seed)
+    return sur
+
+
+def _data(n, seed):
+    x = W.c5_points(n, seed)
+    # a smooth synthetic target over the box (prices of order 80)
+    y = 80 + 10 * np.sin(x[:, 0] / 20) - 5 * x[:, 3] * x[:, 7] + 3 * x[:, 6]
+    return x, y
+
+
+def test_forward_matches_reference():
+    sur = _net()
+    p = sur.get_params().astype(np.float64)
+    x, _ = _data(777, 1)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    yt = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+    sur.infer(xt, yt)
+    ref = mlp.predict(p, x.astype(np.float32).astype(np.float64), LO, HI, 100.0)
+    gpu = yt.cpu().numpy()
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(gpu - ref)) <= 0.03 * scale, (np.max(np.abs(gpu - ref)), scale)
+    assert np.corrcoef(gpu, ref)[0, 1] > 0.999
+
+
+def test_loss_and_gradients_match_reference():
+    sur = _net(seed=3)
+    p = sur.get_params().astype(np.float64)
+    x, y = _data(512, 2)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    yt = torch.tensor(y, dtype=torch.float32, device="cuda")
+    loss, g = sur.loss_grad(xt, yt)
+    rl, rg = mlp.loss_and_grad(p, x.astype(np.float32).astype(np.float64), y.astype(np.float32), LO, HI, 100.0)
+    assert loss == pytest.approx(rl, rel=3e-2)
+    off = 0
+    for o, i in mlp.layer_shapes(8, 256):
+        for size in (o * i, o):
+            a, b = g[off:off + size].astype(np.float64), rg[off:off + size]
+            off += size
+            err = np.linalg.norm(a - b) / np.linalg.norm(b)
+            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+            assert err < 5e-2 and cos > 0.998, (o, i, size, err, cos)
+    assert off == sur.n_params
+
+
+def test_gradients_are_deterministic():
+    sur = _net(seed=4)
+    x, y = _data(1024, 5)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    yt = torch.tensor(y, dtype=torch.float32, device="cuda")
+    l1, g1 = sur.loss_grad(xt, yt)
+    l2, g2 = sur.loss_grad(xt, yt)
+    assert l1 == l2 and np.array_equal(g1, g2)
+
+
+def test_training_reduces_loss():
+    from paper_2108_03076_amd import surrogate as S
+    sur = _net(seed=5)
+    x, y = _data(16384, 6)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    yt = torch.tensor(y, dtype=torch.float32, device="cuda")
+    losses = S.train(sur, xt, yt, epochs=15, batch=512, lr_max=2e-3, lr_min=1e-5)
+    assert losses[-1] < 0.05 * losses[0], losses
+    # parameters really changed on the device and stay finite
+    assert np.all(np.isfinite(sur.get_params()))
+
+
+def test_surrogate_workflow_small():
+    """Labels from the batched engine, training, and the MC judge, at a small
+    scale: the surrogate must beat a constant predictor by a wide margin."""
+    import paper_2108_03076_amd as P
+    from paper_2108_03076_amd import surrogate as S
+    cfg = W.C5
+    pay = P.Payoff(ctx(), cfg.il, cfg.asset_labels, cfg.param_labels, cfg.tvars)
+    xtr = W.c5_points(8192, 42)
+    ytr, _, _, _ = S.mc_prices(pay, xtr, 1 << 12, rate=cfg.rate, years_per_day=cfg.years_per_day, seed=42)
+    xte = W.c5_points(256, 43)
+    yte, sete, _, _ = S.mc_prices(pay, xte, 1 << 14, rate=cfg.rate, years_per_day=cfg.years_per_day, seed=43)
+    sur = _net(seed=6)
+    xt = torch.tensor(xtr, dtype=torch.float32, device="cuda")
+    yt = torch.tensor(ytr, dtype=torch.float32, device="cuda")
+    S.train(sur, xt, yt, epochs=30, batch=512, lr_max=2e-3, lr_min=1e-5)
+    pred = torch.empty(256, dtype=torch.float32, device="cuda")
+    sur.infer(torch.tensor(xte, dtype=torch.float32, device="cuda"), pred)
+    err = S.errors(pred.cpu().numpy(), yte)
+    const = S.errors(np.full(256, ytr.mean()), yte)
+    assert err["rms"] < 0.25 * const["rms"], (err, const)
