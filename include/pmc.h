@@ -113,6 +113,12 @@ int pmc_payoff_load(pmc_ctx* ctx, const char* il_text, size_t len,
                     const char* const* tvar_names, int n_tvars, pmc_payoff** out);
 void pmc_payoff_free(pmc_payoff* p);
 
+/* Time-parameterised payoff (Sec. 4.1, cutPayoff): a new payoff in which
+ * every payoff(t, p, q) is guarded as if(t + t0 < now, 0, payoff(t, p, q)),
+ * so pricing it with opts.t_now = n counts only the cashflows on days >= n
+ * (Thm. 5) without recompiling the contract.  ctx may be NULL. */
+int pmc_payoff_cut(pmc_ctx* ctx, const pmc_payoff* in, pmc_payoff** out);
+
 /* Device source of the compiled payoff engine for this payoff: the engine
  * kernel body plus the payoff expression translated to a HIP device function
  * (compile with -DPMC_REAL=float|double -DPMC_RNG=0|1 -DPMC_A=<assets>

@@ -423,3 +423,34 @@ def parties(e, acc=None):
     elif k == "bin":
         parties(e[2], acc); parties(e[3], acc)
     return acc
+
+
+# ----------------------------------------------------------------------------
+# cutPayoff (Sec. 4.1): guard every payoff with "if (t < now) then 0".
+# ----------------------------------------------------------------------------
+def cut_payoff(e):
+    """cutPayoff of Sec. 4.1.  The paper lists the cases for now, model,
+    unary and binary operators, if and payoff; this reading recurses through
+    every constructor (loopif included) and leaves literals and template
+    values unchanged.  A payoff(t, p, q) becomes
+    if(lt(t(t), now), 0.0, payoff(t, p, q)): the guard compares the payoff's
+    day T[t]delta + t0 with the current time."""
+    k = e[0]
+    if k == "payoff":
+        return ("if", ("bin", "lt", ("texpr", e[1]), ("now",)), ("real", 0.0), e)
+    if k in ("if", "loopif"):
+        return (k, cut_payoff(e[1]), cut_payoff(e[2]), cut_payoff(e[3])) + tuple(e[4:])
+    if k == "un":
+        return ("un", e[1], cut_payoff(e[2]))
+    if k == "bin":
+        return ("bin", e[1], cut_payoff(e[2]), cut_payoff(e[3]))
+    return e
+
+
+def cashflows(e, rho, delta, t, p1, p2, horizon):
+    """Per-day discounted-cashflow weights of a payoff expression that is
+    linear in its payoff nodes (as compiled contracts are, Sec. 4): the value
+    with the discount function replaced by the indicator of day k, for
+    k = 0 .. horizon."""
+    return [float(il_eval(e, rho, delta, 0, t, lambda day, k=k: 1.0 if day == k else 0.0, p1, p2))
+            for k in range(horizon + 1)]

@@ -86,6 +86,7 @@ _sig = {
                              C.POINTER(C.c_char_p), _i, C.POINTER(_vp)]),
     "pmc_payoff_free": (None, [_vp]),
     "pmc_payoff_source": (_i, [_vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "pmc_payoff_cut": (_i, [_vp, _vp, C.POINTER(_vp)]),
     "pmc_payoff_get_info": (_i, [_vp, C.POINTER(PayoffInfo)]),
     "pmc_payoff_grid": (_i, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _i, C.POINTER(_i), C.POINTER(_i)]),
     "pmc_price": (_i, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(Gbm), C.POINTER(Opts),
@@ -212,6 +213,15 @@ class Payoff:
         o = PayoffInfo()
         self.ctx.check(lib.pmc_payoff_get_info(self.h, C.byref(o)))
         return {k: getattr(o, k) for k, _ in o._fields_}
+
+    def cut(self):
+        """The time-parameterised payoff (cutPayoff, Sec. 4.1)."""
+        h = C.c_void_p()
+        self.ctx.check(lib.pmc_payoff_cut(self.ctx.h, self.h, C.byref(h)))
+        new = Payoff.__new__(Payoff)
+        new.h, new.ctx = h, self.ctx
+        new.assets, new.params, new.tvars = self.assets, self.params, self.tvars
+        return new
 
     def source(self):
         """Device source of the compiled engine for this payoff."""

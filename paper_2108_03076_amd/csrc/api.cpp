@@ -182,6 +182,17 @@ extern "C" int pmc_payoff_load(pmc_ctx* c, const char* text, size_t len, const c
 
 extern "C" void pmc_payoff_free(pmc_payoff* p) { delete p; }
 
+extern "C" int pmc_payoff_cut(pmc_ctx* c, const pmc_payoff* in, pmc_payoff** out) {
+  if (!in || !out) return fail(c, PMC_E_ARG, "null argument");
+  auto p = std::make_unique<pmc_payoff>();
+  std::string err;
+  int st = cut_payoff(in->prog, p->prog, err);
+  if (st != PMC_OK) return fail(c, st, err);
+  p->hash = (in->hash ^ 0x9E3779B97F4A7C15ull) * 1099511628211ull;
+  *out = p.release();
+  return PMC_OK;
+}
+
 namespace pmc {
 namespace {
 #include "engine_src.inc"

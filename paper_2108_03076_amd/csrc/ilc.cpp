@@ -420,6 +420,25 @@ struct Encoder {
 
 }  // namespace
 
+// Register allocation and bytecode emission for a typed node tree.
+static int encode(Program& P, std::string& err) {
+  P.code.clear();
+  P.consts.clear();
+  Encoder en(P);
+  en.compute_need(P.root);
+  en.gen(P.root, 0);
+  en.emit(OP_HALT, kTrash, 0, 0, 0);
+  en.emit(OP_HALT, kTrash, 0, 0, 0);   // padding: the interpreter prefetches pc + 1
+  P.n_regs = en.max_reg + 1;
+  P.loop_depth = en.max_depth;
+  if (P.n_regs > kMaxRegs) {
+    err = "expression needs " + std::to_string(P.n_regs) + " registers (limit " + std::to_string(kMaxRegs) + ")";
+    return PMC_E_UNSUPPORTED;
+  }
+  if (P.loop_depth > kMaxLoopDepth) { err = "loopif nested deeper than 8"; return PMC_E_UNSUPPORTED; }
+  return PMC_OK;
+}
+
 int compile(const char* text, size_t len, const std::vector<std::string>& assets,
             const std::vector<std::string>& params, const std::vector<std::string>& tvars,
             Program& out, std::string& err) {
@@ -438,18 +457,45 @@ int compile(const char* text, size_t len, const std::vector<std::string>& assets
   if (root < 0) { err = ps.err; return ps.status; }
   if (P.nodes[root].ty != Ty::R) { err = "payoff expression is not real-valued"; return PMC_E_TYPE; }
   P.root = root;
-  Encoder en(P);
-  en.compute_need(root);
-  en.gen(root, 0);
-  en.emit(OP_HALT, kTrash, 0, 0, 0);
-  en.emit(OP_HALT, kTrash, 0, 0, 0);   // padding: the interpreter prefetches pc + 1
-  P.n_regs = en.max_reg + 1;
-  P.loop_depth = en.max_depth;
-  if (P.n_regs > kMaxRegs) {
-    err = "expression needs " + std::to_string(P.n_regs) + " registers (limit " + std::to_string(kMaxRegs) + ")";
-    return PMC_E_UNSUPPORTED;
+  const int st = encode(P, err);
+  if (st != PMC_OK) return st;
+  out = std::move(P);
+  return PMC_OK;
+}
+
+// cutPayoff (Sec. 4.1): every payoff(t, p, q) becomes
+// if(lt(t(t), now), 0.0, payoff(t, p, q)); the other constructors recurse.
+int cut_payoff(const Program& in, Program& out, std::string& err) {
+  Program P = in;
+  const int n0 = (int)in.nodes.size();
+  for (int i = 0; i < n0; ++i) {
+    if (P.nodes[i].kind != Node::PAYOFF) continue;
+    // keep the payoff as a new node; node i becomes the guard
+    Node pay = P.nodes[i];
+    P.nodes.push_back(pay);
+    const int ipay = (int)P.nodes.size() - 1;
+    Node tx{};
+    tx.kind = Node::TEXPR; tx.ty = Ty::N; tx.tt = pay.tt;
+    P.nodes.push_back(tx);
+    const int itx = (int)P.nodes.size() - 1;
+    Node now{};
+    now.kind = Node::NOW; now.ty = Ty::N;
+    P.nodes.push_back(now);
+    const int inow = (int)P.nodes.size() - 1;
+    Node lt{};
+    lt.kind = Node::BIN; lt.op = OP_LT; lt.ty = Ty::B; lt.kid[0] = itx; lt.kid[1] = inow;
+    P.nodes.push_back(lt);
+    const int ilt = (int)P.nodes.size() - 1;
+    Node zero{};
+    zero.kind = Node::REAL; zero.ty = Ty::R; zero.real = 0.0;
+    P.nodes.push_back(zero);
+    const int izero = (int)P.nodes.size() - 1;
+    Node g{};
+    g.kind = Node::IF; g.ty = Ty::R; g.kid[0] = ilt; g.kid[1] = izero; g.kid[2] = ipay;
+    P.nodes[i] = g;
   }
-  if (P.loop_depth > kMaxLoopDepth) { err = "loopif nested deeper than 8"; return PMC_E_UNSUPPORTED; }
+  const int st = encode(P, err);
+  if (st != PMC_OK) return st;
   out = std::move(P);
   return PMC_OK;
 }

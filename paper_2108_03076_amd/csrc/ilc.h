@@ -47,6 +47,9 @@ int compile(const char* text, size_t len, const std::vector<std::string>& assets
             const std::vector<std::string>& params, const std::vector<std::string>& tvars,
             Program& out, std::string& err);
 
+// cutPayoff of Sec. 4.1 applied to a compiled program (re-encoded).
+int cut_payoff(const Program& in, Program& out, std::string& err);
+
 // Per-template-environment plan: folded time table and simulated grid.
 struct Grid {
   std::vector<int32_t> tt;      // value of every time-table entry

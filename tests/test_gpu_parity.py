@@ -307,3 +307,24 @@ def test_edge_cases_single_path_and_no_slots():
     assert r["price"] == pytest.approx(2 * math.exp(-0.03 * 10 / 252), rel=1e-12)
     r = P.price(cash, [], [], **model_kw(cfg), **opts_kw(cfg, 777, parties=("Y", "X")))
     assert r["price"] == pytest.approx(-2 * math.exp(-0.03 * 10 / 252), rel=1e-12)
+
+
+@pytest.mark.parametrize("engine", ["interpreter", "compiled"])
+def test_time_parameterised_pricing_matches_oracle(engine):
+    """cutPayoff (Sec. 4.1) priced at several current times on the GPU against
+    the oracle's cut expression on the same stream."""
+    import paper_2108_03076_amd as P
+    from oracle.il import cut_payoff, parse
+    from oracle.mc import estimate
+    for cfg, nows in ((_small(W.C3, tenv=[60]), (0, 1, 30, 60, 61)), (W.C2, (0, 1, 3, 5, 6)), (W.C1, (0, 252, 253))):
+        n = 2000
+        pay = gpu_payoff(cfg).cut()
+        for now in nows:
+            print(f"[parity] cut {cfg.name} now={now} {engine}", flush=True)
+            r = P.price(pay, cfg.tenv, cfg.params, **model_kw(cfg), **opts_kw(cfg, n, t_now=now, engine=engine))
+            prob = oracle_problem(cfg, il=cut_payoff(parse(cfg.il)), t_now=now)
+            ref, se = estimate(prob.payoffs(np.arange(n)))
+            if cfg.precision == "f64":
+                assert r["price"] == pytest.approx(ref, rel=1e-12, abs=1e-12)
+            else:
+                assert abs(r["price"] - ref) <= 0.1 * se + 1e-6, (cfg.name, now, r["price"], ref, se)
