@@ -78,6 +78,74 @@ def cpu_baseline(cfg, n_paths):
     return n_paths * len(prob.days) / dt, dt
 
 
+def surrogate_workload(ctx, args):
+    """Labels from the batched Monte Carlo engine (2^16 Philox paths per
+    point), training on the GPU, the Monte Carlo judge (2^22 paths, another
+    seed) on held-out points, and inference against Monte Carlo timing."""
+    import numpy as np
+    import torch
+
+    import paper_2108_03076_amd as P
+    from paper_2108_03076_amd import surrogate as S
+    import workloads as W
+
+    c5 = W.C5
+    pay = P.Payoff(ctx, c5.il, c5.asset_labels, c5.param_labels, c5.tvars)
+    box = W.C5_BOX
+    lo = [box["spot"][0]] * 3 + [box["vol"][0]] * 3 + [box["rho"][0], box["n_obs"][0]]
+    hi = [box["spot"][1]] * 3 + [box["vol"][1]] * 3 + [box["rho"][1], box["n_obs"][1]]
+    rec = {}
+    n_train = args.surrogate_points
+    xtr = W.c5_points(n_train, 42)
+    t0 = time.perf_counter()
+    ytr, setr, pd_tr, ms_tr = S.mc_prices(pay, xtr, c5.n_paths, rate=c5.rate, years_per_day=c5.years_per_day,
+                                          seed=42)
+    rec["label_gen_s"] = time.perf_counter() - t0
+    rec["label_gen_gpu_ms"] = ms_tr
+    rec["label_path_dates"] = int(pd_tr)
+    rec["label_path_dates_per_s_gpu"] = pd_tr / (ms_tr * 1e-3)
+    rec["label_rel_se_median"] = float(np.median(setr / ytr))
+    n_test = c5.notes["test_points"]
+    xte = W.c5_points(n_test, 43)
+    t0 = time.perf_counter()
+    yte, sete, pd_te, ms_te = S.mc_prices(pay, xte, c5.notes["judge_paths"], rate=c5.rate,
+                                          years_per_day=c5.years_per_day, seed=43)
+    rec["judge_s"] = time.perf_counter() - t0
+    rec["judge_rel_se_median"] = float(np.median(sete / yte))
+    sur = P.Surrogate(ctx, lo, hi, y_scale=100.0, width=256, seed=1)
+    xt = torch.tensor(xtr, dtype=torch.float32, device="cuda")
+    yt = torch.tensor(ytr, dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    losses = S.train(sur, xt, yt, epochs=args.surrogate_epochs, batch=4096, lr_max=1e-3, lr_min=1e-5)
+    torch.cuda.synchronize()
+    rec["train_s"] = time.perf_counter() - t0
+    rec["train_loss_first_last"] = [losses[0], losses[-1]]
+    pred = torch.empty(n_test, dtype=torch.float32, device="cuda")
+    sur.infer(torch.tensor(xte, dtype=torch.float32, device="cuda"), pred)
+    rec["error_vs_judge"] = S.errors(pred.cpu().numpy(), yte)
+    rec["error_plain_mc_2^16_vs_judge"] = S.errors(
+        S.mc_prices(pay, xte, c5.n_paths, rate=c5.rate, years_per_day=c5.years_per_day, seed=44)[0], yte)
+    nb = c5.notes["infer_batch"]
+    xb = torch.tensor(W.c5_points(nb, 45), dtype=torch.float32, device="cuda")
+    inf_ms, _ = S.timed_infer(sur, xb)
+    rec["infer_batch"] = nb
+    rec["infer_ms"] = inf_ms
+    flop = 2.0 * (8 * 256 + 2 * 256 * 256 + 256) * nb
+    rec["infer_roofline"] = {"bound": "mfma", "achieved": flop / (inf_ms * 1e-3) / 1e12, "peak": 2500.0,
+                             "unit": "TFLOP/s (bf16 dense)", "frac": flop / (inf_ms * 1e-3) / 2.5e15}
+    # Monte Carlo time for the same batch at 2^16 paths, from the label run's
+    # device throughput; and at the paths giving the surrogate's RMS error
+    mc_ms_2_16 = nb / n_train * ms_tr
+    rec["mc_2^16_ms_same_batch"] = mc_ms_2_16
+    rec["speedup_vs_mc_2^16"] = mc_ms_2_16 / inf_ms
+    rel_se_2_16 = rec["label_rel_se_median"]
+    err = max(rec["error_vs_judge"]["rms"], 1e-9)
+    paths_eq = c5.n_paths * (rel_se_2_16 / err) ** 2
+    rec["mc_paths_at_equal_error"] = paths_eq
+    rec["speedup_vs_mc_equal_error"] = (mc_ms_2_16 * paths_eq / c5.n_paths) / inf_ms
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +153,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="headline workload only, no CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate workload")
+    ap.add_argument("--surrogate-points", type=int, default=1 << 20,
+                    help="training points of the surrogate (each priced by Monte Carlo with 2^16 paths)")
+    ap.add_argument("--surrogate-epochs", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy 256 MiB device-to-device three times (a known-size kernel for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -202,10 +274,12 @@ def main():
         extra["C4_batched_1024"] = {"ms_per_step": s4 * 1e3, "path_dates_per_s": pd4 / s4,
                                     "graph_ms": float(np.mean([r[0]["ms"] for r in o4])),
                                     "path_dates": pd4, "tuned_block": bl, "tuned_paths_per_thread": ppt}
+    if not args.quick and not args.no_surrogate:
+        extra["C5_surrogate"] = surrogate_workload(ctx, args)
     line["workloads"] = extra
 
     if not args.quick and not args.no_cpu_baseline:
-        n_cpu = 1 << 16
+        n_cpu = 1 << 20
         v, dt = cpu_baseline(c2, n_cpu)
         line["cpu_baseline"] = {"value": v, "unit": "path-dates/s", "cores": 1, "kind": "oracle",
                                 "sample": f"first {n_cpu} of the 2^20 Sobol paths of the headline workload "

@@ -321,45 +321,69 @@ struct Tables {
   std::vector<int> n_slots;
 };
 
+// Tables shared by every instance with the same template environment
+// (folded template values, party signs, day map, discount per day, per-slot
+// dt): built once per distinct tenv of a launch.
+struct GridTables {
+  int32_t tt_off, sign_off, daymap_off, horizon, n_slots, dense_first, disc_off, slot_off;
+};
+
 template <typename T>
 int build_instance(pmc_ctx* c, const Program& P, const pmc_gbm& m, const pmc_opts& o,
-                   const InstanceIn& in, int idx, Tables<T>& tb) {
-  Grid g;
-  std::string err;
-  int st = plan(P, in.tenv, g, err);
-  if (st != PMC_OK) return fail(c, st, err);
+                   const InstanceIn& in, int idx, Tables<T>& tb,
+                   std::map<std::vector<int32_t>, GridTables>* memo = nullptr) {
   const int A = (int)P.assets.size();
+  std::vector<int32_t> key(in.tenv, in.tenv + P.tvars.size());
+  GridTables gt{};
+  auto hit = memo ? memo->find(key) : decltype(memo->end()){};
+  if (memo && hit != memo->end()) {
+    gt = hit->second;
+  } else {
+    Grid g;
+    std::string err;
+    int st = plan(P, in.tenv, g, err);
+    if (st != PMC_OK) return fail(c, st, err);
+    gt.tt_off = (int32_t)tb.itab.size();
+    tb.itab.insert(tb.itab.end(), g.tt.begin(), g.tt.end());
+    gt.sign_off = (int32_t)tb.itab.size();
+    for (auto& pr : P.pairs) {
+      const std::string& f = P.parties[pr.first];
+      const std::string& t = P.parties[pr.second];
+      int sg = 0;
+      if (f == o.party_from && t == o.party_to) sg = 1;
+      else if (f == o.party_to && t == o.party_from) sg = -1;
+      tb.itab.push_back(sg);
+    }
+    gt.daymap_off = (int32_t)tb.itab.size();
+    tb.itab.insert(tb.itab.end(), g.daymap.begin(), g.daymap.end());
+    gt.horizon = g.horizon;
+    gt.n_slots = (int32_t)g.days.size();
+    gt.dense_first = 0;
+    if (!g.days.empty() && g.days.back() - g.days.front() + 1 == (int32_t)g.days.size()) gt.dense_first = g.days.front();
+    // d(day) = exp(-r * day * years_per_day)
+    gt.disc_off = (int32_t)tb.rtab.size();
+    for (int32_t day = 0; day <= g.horizon; ++day) tb.rtab.push_back((T)std::exp(-m.rate * (double)day * m.years_per_day));
+    // per slot: dt, sqrt(dt) with dt = (day_s - day_{s-1}) * years_per_day
+    gt.slot_off = (int32_t)tb.rtab.size();
+    int32_t prev = 0;
+    for (int32_t day : g.days) {
+      const double dt = (double)(day - prev) * m.years_per_day;
+      tb.rtab.push_back((T)dt);
+      tb.rtab.push_back((T)std::sqrt(dt));
+      prev = day;
+    }
+    if (memo) (*memo)[key] = gt;
+  }
   InstDesc d{};
-  d.tt_off = (int32_t)tb.itab.size();
-  tb.itab.insert(tb.itab.end(), g.tt.begin(), g.tt.end());
-  d.sign_off = (int32_t)tb.itab.size();
-  for (auto& pr : P.pairs) {
-    const std::string& f = P.parties[pr.first];
-    const std::string& t = P.parties[pr.second];
-    int s = 0;
-    if (f == o.party_from && t == o.party_to) s = 1;
-    else if (f == o.party_to && t == o.party_from) s = -1;
-    tb.itab.push_back(s);
-  }
-  d.daymap_off = (int32_t)tb.itab.size();
-  tb.itab.insert(tb.itab.end(), g.daymap.begin(), g.daymap.end());
-  d.horizon = g.horizon;
-  d.n_slots = (int32_t)g.days.size();
-  d.dense_first = 0;
-  if (!g.days.empty() && g.days.back() - g.days.front() + 1 == (int32_t)g.days.size()) d.dense_first = g.days.front();
+  d.tt_off = gt.tt_off;
+  d.sign_off = gt.sign_off;
+  d.daymap_off = gt.daymap_off;
+  d.horizon = gt.horizon;
+  d.n_slots = gt.n_slots;
+  d.dense_first = gt.dense_first;
+  d.disc_off = gt.disc_off;
+  d.slot_off = gt.slot_off;
   d.t_now = o.t_now;
-  // d(day) = exp(-r * day * years_per_day)
-  d.disc_off = (int32_t)tb.rtab.size();
-  for (int32_t day = 0; day <= g.horizon; ++day) tb.rtab.push_back((T)std::exp(-m.rate * (double)day * m.years_per_day));
-  // per slot: dt, sqrt(dt) with dt = (day_s - day_{s-1}) * years_per_day
-  d.slot_off = (int32_t)tb.rtab.size();
-  int32_t prev = 0;
-  for (int32_t day : g.days) {
-    const double dt = (double)(day - prev) * m.years_per_day;
-    tb.rtab.push_back((T)dt);
-    tb.rtab.push_back((T)std::sqrt(dt));
-    prev = day;
-  }
   d.param_off = (int32_t)tb.rtab.size();
   for (size_t q = 0; q < P.params.size(); ++q) tb.rtab.push_back((T)in.params[q]);
   d.model_off = (int32_t)tb.rtab.size();
@@ -372,9 +396,11 @@ int build_instance(pmc_ctx* c, const Program& P, const pmc_gbm& m, const pmc_opt
   d.instance = in.instance;
   d.n_paths = (uint32_t)std::min<uint64_t>(o.n_paths, 0xFFFFFFFFull);
   if (o.n_paths == (1ull << 32)) return fail(c, PMC_E_UNSUPPORTED, "n_paths = 2^32 is not supported per instance");
-  tb.max_dims = std::max(tb.max_dims, (int)g.days.size() * A);
-  tb.path_dates += (int64_t)o.n_paths * (int64_t)g.days.size();
-  tb.n_slots.push_back((int)g.days.size());
+  if (tb.rtab.size() > 0x7fffffffu || tb.itab.size() > 0x7fffffffu)
+    return fail(c, PMC_E_UNSUPPORTED, "batch tables exceed 2^31 entries");
+  tb.max_dims = std::max(tb.max_dims, (int)gt.n_slots * A);
+  tb.path_dates += (int64_t)o.n_paths * (int64_t)gt.n_slots;
+  tb.n_slots.push_back((int)gt.n_slots);
   tb.desc.push_back(d);
   (void)idx;
   return PMC_OK;
@@ -685,6 +711,7 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
   const int I = b->n_inst;
   Tables<T> tb;
   tb.desc.reserve(I);
+  std::map<std::vector<int32_t>, GridTables> memo;
   for (int i = 0; i < I; ++i) {
     InstanceIn in;
     in.tenv = b->tenv ? b->tenv + (size_t)i * P.tvars.size() : nullptr;
@@ -699,7 +726,7 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
     in.instance = b->instance_ids ? b->instance_ids[i] : (uint32_t)i;
     int st = check_instance(c, P, in);
     if (st != PMC_OK) return st;
-    st = build_instance<T>(c, P, *m, *o, in, i, tb);
+    st = build_instance<T>(c, P, *m, *o, in, i, tb, &memo);
     if (st != PMC_OK) return st;
   }
   // work items (instance, tile), instances with the most slots first; the
