@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 # MI355X published peaks (dense) and the VALU issue rate the ALU roofline uses:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per second.
+METRIC = "path-dates/sec priced (plain MC vs batched/surrogate at \u22640.5% err), % roofline"
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 39.3 T lane-ops/s
 
@@ -172,7 +173,6 @@ def main():
     import paper_2108_03076_amd as P
     import workloads as W
 
-    base = json.load(open(os.path.join(ROOT, "BASELINE.json")))
     ctx = P.Context(0)
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -204,7 +204,7 @@ def main():
     ops = ops_per_path_date(3, "sobol", il_ops) * pd
     achieved = ops / (kern_ms * 1e-3) / 1e12
     line = {
-        "metric": base["metric"],
+        "metric": METRIC,
         "value": value,
         "unit": "path-dates/s",
         "n_gpus": 1,
