@@ -117,9 +117,11 @@ def surrogate_workload(ctx, args):
     xt = torch.tensor(xtr, dtype=torch.float32, device="cuda")
     yt = torch.tensor(ytr, dtype=torch.float32, device="cuda")
     t0 = time.perf_counter()
-    losses = S.train(sur, xt, yt, epochs=args.surrogate_epochs, batch=4096, lr_max=1e-3, lr_min=1e-5)
+    losses = S.train(sur, xt, yt, epochs=args.surrogate_epochs, batch=args.surrogate_batch,
+                     lr_max=args.surrogate_lr, lr_min=1e-5)
     torch.cuda.synchronize()
     rec["train_s"] = time.perf_counter() - t0
+    rec["train_epochs_batch_lr"] = [args.surrogate_epochs, args.surrogate_batch, args.surrogate_lr]
     rec["train_loss_first_last"] = [losses[0], losses[-1]]
     pred = torch.empty(n_test, dtype=torch.float32, device="cuda")
     sur.infer(torch.tensor(xte, dtype=torch.float32, device="cuda"), pred)
@@ -157,7 +159,9 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate workload")
     ap.add_argument("--surrogate-points", type=int, default=1 << 20,
                     help="training points of the surrogate (each priced by Monte Carlo with 2^16 paths)")
-    ap.add_argument("--surrogate-epochs", type=int, default=20)
+    ap.add_argument("--surrogate-epochs", type=int, default=60)
+    ap.add_argument("--surrogate-batch", type=int, default=4096)
+    ap.add_argument("--surrogate-lr", type=float, default=2e-3, help="peak of the cosine learning-rate schedule")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy 256 MiB device-to-device three times (a known-size kernel for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters)")

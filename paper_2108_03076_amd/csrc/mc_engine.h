@@ -304,6 +304,7 @@ struct MemSource {
     paths = g.paths;
     spotp = K(g.rtab) + d.model_off + 2 * A;
   }
+  // Loads slots s .. s+WS-1 (clamped) with WS * A independent loads.
   __device__ __forceinline__ void refill(T (&win)[kWindow], int s) {
     const int last = n_slots - 1;
 #pragma unroll
