@@ -43,6 +43,32 @@ OPS_SOBOL = 1            # one XOR per point with Gray-code stepping
 OPS_PHILOX = 15          # 10 rounds x (2 mul-hi, 2 mul-lo, 2 xor3) / 4 words
 
 
+# HBM traffic of the headline kernel per launch, from two rocprofv3 --pmc
+# passes (FETCH_SIZE, WRITE_SIZE: KiB per dispatch) scaled by what the same
+# counters read for a 256 MiB device-to-device copy in the same run (FETCH
+# reads 0.5 KiB per KiB copied, WRITE 1.0).  Valid only for the engine sources
+# it was measured on (hash below); otherwise reported as null.
+TRAFFIC = {"engine_sha256": None, "fetch_kib": None, "write_kib": None, "fetch_scale": 2.0, "write_scale": 1.0}
+ENGINE_SOURCES = ("paper_2108_03076_amd/csrc/mc_engine.h", "paper_2108_03076_amd/csrc/pmc_device.h",
+                  "paper_2108_03076_amd/csrc/codegen.cpp")
+
+
+def engine_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ENGINE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    t = TRAFFIC
+    if t["engine_sha256"] is None or t["engine_sha256"] != engine_sha256():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
 def ops_per_path_date(n_assets, rng, il_ops_per_date):
     word = OPS_SOBOL if rng == "sobol" else OPS_PHILOX
     corr = (n_assets + 1) / 2 if n_assets > 1 else 0
@@ -72,10 +98,12 @@ def cpu_baseline(cfg, n_paths):
                       params=cfg.params, tenv=cfg.tenv_dict(), spot=cfg.spot, vol=cfg.vol, corr=cfg.corr,
                       rate=cfg.rate, years_per_day=cfg.years_per_day, rng=cfg.rng, seed=cfg.seed,
                       precision=cfg.precision)
-    t0 = time.perf_counter()
-    pay = prob.payoffs(np.arange(n_paths))
-    mc.estimate(pay)
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):      # one core: BLAS and OpenMP pools pinned to one thread
+        t0 = time.perf_counter()
+        pay = prob.payoffs(np.arange(n_paths))
+        mc.estimate(pay)
+        dt = time.perf_counter() - t0
     return n_paths * len(prob.days) / dt, dt
 
 
@@ -228,7 +256,7 @@ def main():
         "engine": "compiled payoff (hipRTC)",
         "roofline": {"bound": "alu", "kernel": "pmc_jit_mc<float,sobol,3 assets> (fused, compiled payoff)",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "T lane-op/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(),
                      "kernel_ms": kern_ms, "algorithmic_ops_per_launch": ops},
     }
 
@@ -278,16 +306,27 @@ def main():
         extra["C4_batched_1024"] = {"ms_per_step": s4 * 1e3, "path_dates_per_s": pd4 / s4,
                                     "graph_ms": float(np.mean([r[0]["ms"] for r in o4])),
                                     "path_dates": pd4, "tuned_block": bl, "tuned_paths_per_thread": ppt}
+        # Risk: delta, gamma and vega of the same 1024 instruments by central
+        # differences on common random numbers, 1 + 4A = 5 scenarios each in
+        # one persistent launch
+        bumps = W.RISK_BUMPS
+        sr, orr = time_steps(lambda: P.risk_batch(pay4, tenv, params, **bumps, **kw4), max(2, args.steps // 10), 1)
+        n_scen = 1024 * 5
+        pd_r = n_scen // 1024 * pd4
+        extra["C4_risk_1024x5"] = {"ms_per_step": sr * 1e3, "pricings_per_s": n_scen / sr,
+                                   "greeks_per_s": 3 * 1024 / sr, "path_dates_per_s": pd_r / sr,
+                                   "graph_ms": float(np.mean([r[0]["ms"] for r in orr])),
+                                   "bumps": bumps, "instrument_0": orr[-1][0]}
     if not args.quick and not args.no_surrogate:
         extra["C5_surrogate"] = surrogate_workload(ctx, args)
     line["workloads"] = extra
 
     if not args.quick and not args.no_cpu_baseline:
-        n_cpu = 1 << 20
+        n_cpu = 1 << 18
         v, dt = cpu_baseline(c2, n_cpu)
         line["cpu_baseline"] = {"value": v, "unit": "path-dates/s", "cores": 1, "kind": "oracle",
                                 "sample": f"first {n_cpu} of the 2^20 Sobol paths of the headline workload "
-                                          f"({dt:.1f} s, FP64, single-threaded Python)",
+                                          f"({dt:.1f} s, FP64 numpy, one thread)",
                                 "host": platform.processor() or platform.machine(),
                                 "cpu_count": os.cpu_count()}
     ctx.close()

@@ -132,6 +132,9 @@ typedef struct pmc_payoff_info {
   int loop_depth;   /* deepest loopif nesting */
   int n_time_exprs; /* distinct template expressions (folded per tenv) */
   int n_parties;    /* distinct party names */
+  int n_assets;     /* model observables the payoff was loaded with */
+  int n_params;     /* parameter observables */
+  int n_tvars;      /* template variables */
 } pmc_payoff_info;
 int pmc_payoff_get_info(const pmc_payoff* p, pmc_payoff_info* out);
 
@@ -230,6 +233,33 @@ int pmc_price_batch(pmc_ctx* ctx, const pmc_payoff* p, const pmc_batch* batch,
 int pmc_autotune_batch(pmc_ctx* ctx, const pmc_payoff* p, const pmc_batch* batch,
                        const pmc_gbm* model, const pmc_opts* opts, const char* cache_path,
                        int* block_out, int* ppt_out);
+
+/* Bump-and-revalue risk over a batch (the risk runs of thousands of
+ * pricings of one compiled contract that motivate the engine, Sec. 7).
+ * For every instance of the batch (same layout and model rules as
+ * pmc_price_batch) the library prices 1 + 4A scenarios: the base model, then
+ * for each asset a the spots S_a + h_a and S_a - h_a (h_a = rel_spot_bump *
+ * S_a), then for each asset the volatilities sigma_a + k and sigma_a - k
+ * (k = abs_vol_bump).  All scenarios of an instance use the instance's random
+ * stream (common random numbers) and run as one persistent batch launch.
+ * Central differences give delta_a = (V+ - V-) / 2h_a, gamma_a =
+ * (V+ - 2V + V-) / h_a^2 and vega_a = (V+ - V-) / 2k.  out[n_inst]; entries
+ * beyond A are zero; ms is the device time of the whole launch.
+ * Errors: those of pmc_price_batch; PMC_E_ARG if 0 < rel_spot_bump < 1 and
+ * 0 < abs_vol_bump < sigma_a do not hold. */
+typedef struct pmc_risk_opts {
+  double rel_spot_bump;
+  double abs_vol_bump;
+} pmc_risk_opts;
+typedef struct pmc_greeks {
+  double price, std_err;
+  double delta[PMC_MAX_ASSETS];
+  double gamma[PMC_MAX_ASSETS];
+  double vega[PMC_MAX_ASSETS];
+  double ms;
+} pmc_greeks;
+int pmc_risk_batch(pmc_ctx* ctx, const pmc_payoff* p, const pmc_batch* batch, const pmc_gbm* model,
+                   const pmc_opts* opts, const pmc_risk_opts* risk, pmc_greeks* out);
 
 /* Parity hooks.  pmc_gen_paths writes the simulated prices S[slot][asset][path]
  * (float or double by opts.precision) to paths_dev, and optionally the raw

@@ -50,3 +50,22 @@ def down_and_out_call(S, K, B, r, sigma, T):
 def bgk_barrier(B, sigma, dt):
     """Barrier shift for discrete monitoring (down barrier moves down)."""
     return B * math.exp(-BGK_BETA * sigma * math.sqrt(dt))
+
+
+def _d1(S, K, r, sigma, T):
+    return (math.log(S / K) + (r + 0.5 * sigma * sigma) * T) / (sigma * math.sqrt(T))
+
+
+def bs_call_delta(S, K, r, sigma, T):
+    """dC/dS = N(d1)."""
+    return _N(_d1(S, K, r, sigma, T))
+
+
+def bs_call_gamma(S, K, r, sigma, T):
+    """d2C/dS2 = phi(d1) / (S sigma sqrt(T))."""
+    return NormalDist().pdf(_d1(S, K, r, sigma, T)) / (S * sigma * math.sqrt(T))
+
+
+def bs_call_vega(S, K, r, sigma, T):
+    """dC/dsigma = S phi(d1) sqrt(T)."""
+    return S * NormalDist().pdf(_d1(S, K, r, sigma, T)) * math.sqrt(T)

@@ -67,7 +67,17 @@ class Batch(C.Structure):
 
 class PayoffInfo(C.Structure):
     _fields_ = [("n_instr", C.c_int), ("n_regs", C.c_int), ("loop_depth", C.c_int),
-                ("n_time_exprs", C.c_int), ("n_parties", C.c_int)]
+                ("n_time_exprs", C.c_int), ("n_parties", C.c_int), ("n_assets", C.c_int),
+                ("n_params", C.c_int), ("n_tvars", C.c_int)]
+
+
+class RiskOpts(C.Structure):
+    _fields_ = [("rel_spot_bump", C.c_double), ("abs_vol_bump", C.c_double)]
+
+
+class Greeks(C.Structure):
+    _fields_ = [("price", C.c_double), ("std_err", C.c_double), ("delta", C.c_double * 4),
+                ("gamma", C.c_double * 4), ("vega", C.c_double * 4), ("ms", C.c_double)]
 
 
 class TrainOpts(C.Structure):
@@ -92,6 +102,8 @@ _sig = {
     "pmc_price": (_i, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(Gbm), C.POINTER(Opts),
                        C.POINTER(Result)]),
     "pmc_price_batch": (_i, [_vp, _vp, C.POINTER(Batch), C.POINTER(Gbm), C.POINTER(Opts), C.POINTER(Result)]),
+    "pmc_risk_batch": (_i, [_vp, _vp, C.POINTER(Batch), C.POINTER(Gbm), C.POINTER(Opts), C.POINTER(RiskOpts),
+                            C.POINTER(Greeks)]),
     "pmc_autotune_batch": (_i, [_vp, _vp, C.POINTER(Batch), C.POINTER(Gbm), C.POINTER(Opts), C.c_char_p,
                                 C.POINTER(_i), C.POINTER(_i)]),
     "pmc_gen_paths": (_i, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(Gbm), C.POINTER(Opts), _vp, _vp, _vp]),
@@ -405,6 +417,26 @@ def price_batch(payoff: Payoff, tenv, params, *, spot, vol, corr=None, rate=0.03
     out = (Result * n)()
     payoff.ctx.check(lib.pmc_price_batch(payoff.ctx.h, payoff.h, C.byref(b), C.byref(g), C.byref(o), out))
     return [r.as_dict() for r in out]
+
+
+def risk_batch(payoff: Payoff, tenv, params, *, spot, vol, corr=None, rate=0.03, years_per_day=1.0,
+               per_instance_model=False, instance_ids=None, rel_spot_bump=0.01, abs_vol_bump=0.01, **opts):
+    """Bump-and-revalue Greeks of every instance on common random numbers
+    (pmc_risk_batch): a list of dicts with price, std_err, delta[A],
+    gamma[A], vega[A] and ms."""
+    b, n, keep = _batch(payoff, tenv, params, spot, vol, corr, per_instance_model, instance_ids)
+    A = len(payoff.assets)
+    if per_instance_model:
+        g, keep2 = make_model([100.0] * A, [0.0] * A, None, rate, years_per_day)
+    else:
+        g, keep2 = make_model(spot, vol, corr, rate, years_per_day)
+    o = make_opts(**opts)
+    r = RiskOpts(float(rel_spot_bump), float(abs_vol_bump))
+    out = (Greeks * n)()
+    payoff.ctx.check(lib.pmc_risk_batch(payoff.ctx.h, payoff.h, C.byref(b), C.byref(g), C.byref(o), C.byref(r),
+                                        out))
+    return [{"price": x.price, "std_err": x.std_err, "delta": list(x.delta)[:A], "gamma": list(x.gamma)[:A],
+             "vega": list(x.vega)[:A], "ms": x.ms} for x in out]
 
 
 def autotune_batch(payoff: Payoff, tenv, params, *, spot, vol, corr=None, rate=0.03, years_per_day=1.0,

@@ -42,15 +42,18 @@ struct DevBuf {
 
 struct HostPinned {
   void* p = nullptr;
+  void* dev = nullptr;   // the device's address of the same memory
   size_t cap = 0;
+  unsigned flags = hipHostMallocDefault;
   ~HostPinned() { if (p) (void)hipHostFree(p); }
   hipError_t ensure(size_t n) {
     if (n <= cap) return hipSuccess;
-    if (p) { (void)hipHostFree(p); p = nullptr; cap = 0; }
+    if (p) { (void)hipHostFree(p); p = nullptr; dev = nullptr; cap = 0; }
     size_t want = std::max<size_t>(n, 4096);
-    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
-    if (e == hipSuccess) cap = want;
-    return e;
+    hipError_t e = hipHostMalloc(&p, want, flags);
+    if (e != hipSuccess) return e;
+    cap = want;
+    return hipHostGetDevicePointer(&dev, p, 0);
   }
 };
 
@@ -78,7 +81,10 @@ struct pmc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  DevBuf blob, partial, result, bad, queue, paths, sobol, chol, sobol_hi;
+  DevBuf blob, partial, bad, counters, paths, sobol, chol, sobol_hi;
+  // Results, written by the kernels straight into coherent host memory:
+  // n_inst (sum, sum of squares) pairs, then n_inst Cholesky status words.
+  HostPinned results{nullptr, nullptr, 0, hipHostMallocCoherent | hipHostMallocMapped};
   int sobol_hi_rows = 0, sobol_hi_dims = 0, sobol_hi_bits = 0;
   std::vector<uint8_t> last_upload;   // bytes the blob holds (skip identical uploads)
   HostPinned staging;
@@ -95,6 +101,7 @@ struct pmc_payoff {
   Program prog;
   uint64_t hash = 0;
   mutable JitCache jit;   // compiled-engine kernels, built on first use
+  mutable std::map<std::vector<int32_t>, int64_t> fused_cost;   // per template environment
 };
 
 // Errors of calls made without a context (payoff loading may run before
@@ -218,6 +225,9 @@ extern "C" int pmc_payoff_get_info(const pmc_payoff* p, pmc_payoff_info* o) {
   o->loop_depth = p->prog.loop_depth;
   o->n_time_exprs = (int)p->prog.tt.size();
   o->n_parties = (int)p->prog.parties.size();
+  o->n_assets = (int)p->prog.assets.size();
+  o->n_params = (int)p->prog.params.size();
+  o->n_tvars = (int)p->prog.tvars.size();
   return PMC_OK;
 }
 
@@ -244,16 +254,17 @@ extern "C" int pmc_cholesky(pmc_ctx* c, const double* a, int n, int m, double* l
   HIP_TRY(c, c->blob.ensure(bytes));
   c->last_upload.clear();   // the blob is reused for the input below
   HIP_TRY(c, c->chol.ensure(bytes));
-  HIP_TRY(c, c->bad.ensure(sizeof(int)));
-  const int big = 0x7fffffff;
-  HIP_TRY(c, hipMemcpyAsync(c->bad.p, &big, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, c->bad.ensure((size_t)n * sizeof(int)));
   HIP_TRY(c, hipMemcpyAsync(c->blob.p, a, bytes, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, launch_cholesky((const double*)c->blob.p, (double*)c->chol.p, (int*)c->bad.p, n, m, c->stream));
-  int bad = 0;
-  HIP_TRY(c, hipMemcpyAsync(&bad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, launch_prep((const double*)c->blob.p, (double*)c->chol.p, (int*)c->bad.p, nullptr, 0, n, m, c->stream));
+  std::vector<int> status(n);
+  HIP_TRY(c, hipMemcpyAsync(status.data(), c->bad.p, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(l, c->chol.p, bytes, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (bad != big) return fail(c, PMC_E_NOT_PD, "matrix " + std::to_string(bad) + " is not positive definite");
+  int bad = -1;
+  for (int i = 0; i < n && bad < 0; ++i)
+    if (status[i]) bad = i;
+  if (bad >= 0) return fail(c, PMC_E_NOT_PD, "matrix " + std::to_string(bad) + " is not positive definite");
   return PMC_OK;
 }
 
@@ -487,7 +498,9 @@ int upload(pmc_ctx* c, const Program& P, const Tables<T>& tb, const pmc_opts& o,
   L.n_regs = P.n_regs;
   L.ppt = 1;
   if (o.rng == PMC_RNG_SOBOL) {
-    int st = ensure_sobol(c, tb.max_dims);
+    // at least one dimension, so that the direction-number table exists even
+    // for an expression that simulates no day (the kernels read it regardless)
+    int st = ensure_sobol(c, std::max(1, tb.max_dims));
     if (st != PMC_OK) return st;
     L.sobol = (const uint32_t*)c->sobol.p;
     L.sobol_bits = sobol_bits(o.n_paths);
@@ -500,26 +513,41 @@ int upload(pmc_ctx* c, const Program& P, const Tables<T>& tb, const pmc_opts& o,
   return PMC_OK;
 }
 
-// The result buffer holds n_inst (sum, sum of squares) pairs followed by the
-// Cholesky status word, so one copy returns both.
-int* status_word(pmc_ctx* c, int n_inst) { return (int*)((char*)c->result.p + (size_t)n_inst * sizeof(double2)); }
-
-int factor(pmc_ctx* c, const McLaunch& L, int n_inst, int A) {
-  HIP_TRY(c, c->result.ensure((size_t)(n_inst + 1) * sizeof(double2)));
-  int* bad = status_word(c, n_inst);
-  HIP_TRY(c, launch_fill_u32((uint32_t*)bad, 0x7fffffffu, 1, c->stream));
-  HIP_TRY(c, launch_cholesky(L.chol_in, (double*)c->chol.p, bad, n_inst, A, c->stream));
+// Result and counter buffers for n_inst instances; fills the launch's
+// result, done and (persistent launches) queue pointers.
+int bind_results(pmc_ctx* c, McLaunch& L, int n_inst, bool persistent) {
+  HIP_TRY(c, c->results.ensure((size_t)n_inst * (sizeof(double2) + sizeof(int))));
+  HIP_TRY(c, c->counters.ensure((size_t)(n_inst + 1) * sizeof(uint32_t)));
+  L.result = (double2*)c->results.dev;
+  L.done = (uint32_t*)c->counters.p;
+  L.queue = persistent ? L.done + n_inst : nullptr;
   return PMC_OK;
 }
 
+int* status_dev(pmc_ctx* c, int n_inst) { return (int*)((double2*)c->results.dev + n_inst); }
+const int* status_host(pmc_ctx* c, int n_inst) { return (const int*)((const double2*)c->results.p + n_inst); }
+
+// Zeroes the counters and factors the instances' correlation matrices.
+int prep(pmc_ctx* c, const McLaunch& L, int n_inst, int A) {
+  HIP_TRY(c, launch_prep(L.chol_in, (double*)c->chol.p, status_dev(c, n_inst), L.done, n_inst + 1, n_inst, A,
+                         c->stream));
+  return PMC_OK;
+}
+
+int first_bad(pmc_ctx* c, int n_inst) {
+  const int* st = status_host(c, n_inst);
+  for (int i = 0; i < n_inst; ++i)
+    if (st[i]) return i;
+  return -1;
+}
+
+// Reads the results the kernels wrote to host memory; the caller has
+// synchronized with the launch.
 int finish(pmc_ctx* c, int n_inst, const std::vector<uint64_t>& n_paths, const std::vector<int>& n_slots,
            int mode_used, double ms, pmc_result* out, double gen_ms = 0.0, double eval_ms = 0.0) {
-  std::vector<double2> res(n_inst + 1);
-  HIP_TRY(c, hipMemcpyAsync(res.data(), c->result.p, (n_inst + 1) * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  int bad = 0;
-  std::memcpy(&bad, &res[n_inst], sizeof(int));
-  if (bad != 0x7fffffff) return fail(c, PMC_E_NOT_PD, "correlation matrix of instance " + std::to_string(bad) + " is not positive definite");
+  const int bad = first_bad(c, n_inst);
+  if (bad >= 0) return fail(c, PMC_E_NOT_PD, "correlation matrix of instance " + std::to_string(bad) + " is not positive definite");
+  const double2* res = (const double2*)c->results.p;
   for (int i = 0; i < n_inst; ++i) {
     const double N = (double)n_paths[i];
     pmc_result r{};
@@ -578,10 +606,15 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
     mode = PMC_MODE_TWO_PHASE;
   } else if (mode == PMC_MODE_AUTO) {
     // fused unless the window would regenerate much more than one path
-    Grid g;
-    std::string err;
-    plan(P, tenv, g, err);
-    int64_t cost = fused_generation_cost(P, g, A, 1 << 22);
+    std::vector<int32_t> key(tenv, tenv + P.tvars.size());
+    auto it = p->fused_cost.find(key);
+    if (it == p->fused_cost.end()) {
+      Grid g;
+      std::string err;
+      plan(P, tenv, g, err);
+      it = p->fused_cost.emplace(key, fused_generation_cost(P, g, A, 1 << 22)).first;
+    }
+    const int64_t cost = it->second;
     mode = (cost >= 0 && cost <= 2 * (int64_t)std::max(1, n_slots)) ? PMC_MODE_FUSED : PMC_MODE_TWO_PHASE;
   }
   const uint32_t tiles = (uint32_t)((N + block - 1) / block);
@@ -591,12 +624,13 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   st = upload<T>(c, P, tb, *o, L, nullptr);
   if (st != PMC_OK) return st;
   HIP_TRY(c, c->partial.ensure((size_t)tiles * sizeof(double2)));
-  HIP_TRY(c, c->result.ensure(2 * sizeof(double2)));
+  st = bind_results(c, L, 1, false);
+  if (st != PMC_OK) return st;
   L.partial = (double2*)c->partial.p;
   L.n_work = (int)tiles;
   L.payoff_out = o->payoffs_dev;
   HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-  st = factor(c, L, 1, A);
+  st = prep(c, L, 1, A);
   if (st != PMC_OK) return st;
   const int prec = sizeof(T) == 8 ? 1 : 0;
   HIP_TRY(c, hipEventRecord(c->evk[0], c->stream));
@@ -618,7 +652,6 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   }
   if (st != PMC_OK) return st;
   HIP_TRY(c, hipEventRecord(c->evk[2], c->stream));
-  HIP_TRY(c, launch_reduce(L.partial, L.desc, 1, (double2*)c->result.p, c->stream));
   HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
   HIP_TRY(c, hipEventSynchronize(c->ev1));
   float ms = 0, gen_ms = 0, eval_ms = 0;
@@ -670,13 +703,12 @@ int gen_paths(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const pmc_gb
   McLaunch L;
   st = upload<T>(c, P, tb, *o, L, nullptr);
   if (st != PMC_OK) return st;
-  st = factor(c, L, 1, (int)P.assets.size());
+  st = bind_results(c, L, 1, false);
+  if (st == PMC_OK) st = prep(c, L, 1, (int)P.assets.size());
   if (st != PMC_OK) return st;
   HIP_TRY(c, launch_pathgen(sizeof(T) == 8 ? 1 : 0, o->rng, L, paths, words, normals, (uint32_t)o->n_paths, 256, c->stream));
-  int bad = 0;
-  HIP_TRY(c, hipMemcpyAsync(&bad, status_word(c, 1), sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (bad != 0x7fffffff) return fail(c, PMC_E_NOT_PD, "correlation matrix is not positive definite");
+  if (first_bad(c, 1) >= 0) return fail(c, PMC_E_NOT_PD, "correlation matrix is not positive definite");
   return PMC_OK;
 }
 }  // namespace
@@ -749,15 +781,23 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
   if (st != PMC_OK) return st;
   L.tiles = (int)tiles;
   HIP_TRY(c, c->partial.ensure(n_work * sizeof(double2)));
-  HIP_TRY(c, c->result.ensure((size_t)(I + 1) * sizeof(double2)));
-  HIP_TRY(c, c->queue.ensure(sizeof(uint32_t)));
+  st = bind_results(c, L, I, true);
+  if (st != PMC_OK) return st;
   L.partial = (double2*)c->partial.p;
   L.n_work = (int)n_work;
-  L.queue = (uint32_t*)c->queue.p;
   L.ppt = ppt;
   L.payoff_out = nullptr;
   bp.L = L;
-  const int occ = mc_occupancy(sizeof(T) == 8 ? 1 : 0, o->rng, A, P.n_regs, block);
+  int occ = 1;
+  if (o->engine == PMC_ENGINE_INTERPRETER) {
+    occ = mc_occupancy(sizeof(T) == 8 ? 1 : 0, o->rng, A, P.n_regs, block);
+  } else {   // the generated kernel's own register and LDS use
+    hipFunction_t f = nullptr;
+    std::string err;
+    st = p->jit.get(P, c->device, sizeof(T) == 8 ? 1 : 0, o->rng, A, false, &f, err);
+    if (st != PMC_OK) return fail(c, st, err);
+    occ = mc_occupancy_jit(f, block);
+  }
   bp.grid = std::max(1, std::min<int>((int)n_work, c->n_cu * occ));
   bp.block = block; bp.ppt = ppt; bp.n_inst = I;
   bp.n_paths.assign(I, N);
@@ -766,17 +806,13 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
   return PMC_OK;
 }
 
-// Enqueue the batched sequence: Cholesky factors, queue reset, persistent
-// MC kernel, per-instance reduction.  Captured once into a graph.
+// Enqueue the batched sequence: counter reset and Cholesky factors, then the
+// persistent MC kernel (which also reduces each instance).  Captured once
+// into a graph.
 int batch_enqueue(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, const BatchPlan& bp, int prec, int A) {
-  int st = factor(c, bp.L, bp.n_inst, A);
+  int st = prep(c, bp.L, bp.n_inst, A);
   if (st != PMC_OK) return st;
-  const McLaunch& L = bp.L;
-  HIP_TRY(c, launch_fill_u32(L.queue, 0u, 1, c->stream));
-  st = launch_engine(c, p, o, prec, false, L, bp.grid, bp.block);
-  if (st != PMC_OK) return st;
-  HIP_TRY(c, launch_reduce(L.partial, L.desc, bp.n_inst, (double2*)c->result.p, c->stream));
-  return PMC_OK;
+  return launch_engine(c, p, o, prec, false, bp.L, bp.grid, bp.block);
 }
 
 int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_opts* o, float* ms_out) {
@@ -784,7 +820,7 @@ int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_op
   const int A = (int)p->prog.assets.size();
   std::ostringstream key;
   key << p->hash << ':' << bp.n_inst << ':' << bp.grid << ':' << bp.block << ':' << bp.ppt << ':' << bp.L.n_work
-      << ':' << prec << ':' << o->rng << ':' << o->engine << ':' << c->blob.p << ':' << c->partial.p << ':' << c->result.p << ':'
+      << ':' << prec << ':' << o->rng << ':' << o->engine << ':' << c->blob.p << ':' << c->partial.p << ':' << c->results.dev << ':' << c->counters.p << ':'
       << c->chol.p << ':' << c->sobol.p << ':' << (const void*)bp.L.sobol_hi << ':' << (const void*)bp.L.desc << ':'
       << (const void*)bp.L.order;
   if (c->graph.key != key.str()) {

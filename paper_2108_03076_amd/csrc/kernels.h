@@ -27,6 +27,8 @@ struct McLaunch {
   int n_work;
   uint32_t* queue;            // work counter (persistent launch) or nullptr
   double2* partial;           // per item: (sum, sum of squares)
+  uint32_t* done;             // per instance: finished-tile counter (zeroed by launch_prep)
+  double2* result;            // per instance: (sum, sum of squares); may be mapped host memory
   void* payoff_out;           // optional per-path payoffs of instance 0
   const void* paths;          // stored prices [slot][asset][path] (two-phase)
   uint32_t k0, k1;            // Philox key
@@ -41,13 +43,14 @@ hipError_t launch_mc(int precision, int rng, bool from_memory, const McLaunch& a
 hipError_t launch_mc_jit(hipFunction_t f, int precision, const McLaunch& a, int grid, int block, hipStream_t s);
 hipError_t launch_pathgen(int precision, int rng, const McLaunch& a, void* paths, uint32_t* words,
                           void* normals, uint32_t n_paths, int block, hipStream_t s);
-hipError_t launch_reduce(const double2* partial, const InstDesc* desc, int n_inst, double2* out,
-                         hipStream_t s);
-hipError_t launch_cholesky(const double* a, double* l, int* bad, int n, int m, hipStream_t s);
-hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s);
+// Zeroes zero[0..n_zero) and factors the n correlation matrices a (m x m,
+// FP64) into l; status[i] = 0 if matrix i is positive definite, else 1.
+hipError_t launch_prep(const double* a, double* l, int* status, uint32_t* zero, int n_zero, int n, int m,
+                       hipStream_t s);
 // hi[h][d] = XOR of sobol[d][b] over the set bits b >= 6 of gray(64 h).
 hipError_t launch_sobol_hi(const uint32_t* sobol, uint32_t* hi, int n_rows, int dims, int bits, hipStream_t s);
 // Largest resident blocks per CU for the persistent MC kernel.
 int mc_occupancy(int precision, int rng, int n_assets, int n_regs, int block);
+int mc_occupancy_jit(hipFunction_t f, int block);
 
 }  // namespace pmc

@@ -16,8 +16,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
                                               uint32_t k0, uint32_t k1, uint32_t out[4]) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    // one 32x32->64 product each (a single v_mad_u64_u32)
+    const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u, p1 = (uint64_t)c2 * 0xCD9E8D57u;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     c0 = hi1 ^ c1 ^ k0;
     c1 = lo1;
     c2 = hi0 ^ c3 ^ k1;
@@ -31,37 +33,51 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 // ---------------------------------------------- uniforms and normals -----
 template <typename T> struct Num;
 
-// FP32: u = (x>>9 + 1/2) 2^-23 (exact in binary32); Phi^-1 by AS241's
-// 7-digit variant PPND7 (Wichura 1988).
+// FP32: u = (x>>9 + 1/2) 2^-23 (exact in binary32, 2^-24 <= u <= 1 - 2^-24).
+// Phi^-1 through the change of variable of Giles ("Approximating the erfinv
+// function", 2011): w = -ln(4u(1-u)), z = (2u-1) g(w), with g a polynomial in
+// w - 2.5 for w < 5 and in sqrt(w) - c for the tail (w <= 15.25 for these
+// uniforms).  Our own coefficients, fitted by paper_2108_03076_amd/fit_normal.py;
+// |z - Phi^-1(u)| <= 3e-7 max(1, |z|) over the binary32 uniforms.
 template <> struct Num<float> {
   static __device__ __forceinline__ float uniform(uint32_t x) {
     return fmaf((float)(x >> 9), 0x1p-23f, 0x1p-24f);
   }
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-  static __device__ __forceinline__ float normal(float p) {
-    const float q = p - 0.5f;
-    // central region |q| <= 0.425
-    const float r = 0.180625f - q * q;
-    const float nc = q * fmaf(fmaf(fmaf(59.109374720f, r, 159.29113202f), r, 50.434271938f), r, 3.3871327179f);
-    const float dc = fmaf(fmaf(fmaf(67.187563600f, r, 78.757757664f), r, 17.895169469f), r, 1.0f);
-    // tails: r = sqrt(-log(min(p, 1-p))); 1-p is exact for our uniforms
-    const float pt = fminf(p, 1.0f - p);
-    const float rt = __builtin_sqrtf(-__logf(pt));
-    float s = rt - 1.6f;
-    float nt = fmaf(fmaf(fmaf(0.17023821103f, s, 1.3067284816f), s, 2.7568153900f), s, 1.4234372777f);
-    float dt = fmaf(fmaf(0.12021132975f, s, 0.73700164250f), s, 1.0f);
-    const bool far = rt > 5.0f;
-    if (__any(far)) {   // min(p,1-p) < e^-25: unreachable for 23-bit uniforms, kept for completeness
-      const float e = rt - 5.0f;
-      const float ne = fmaf(fmaf(fmaf(0.017337203997f, e, 0.42868294337f), e, 3.0812263860f), e, 6.6579051150f);
-      const float de = fmaf(fmaf(0.012258202635f, e, 0.24197894225f), e, 1.0f);
-      nt = far ? ne : nt;
-      dt = far ? de : dt;
+  static __device__ __forceinline__ float normal_word(uint32_t x) {
+    // f = 1 + (x >> 9) 2^-23; u = f - (1 - 2^-24) is exact (Sterbenz), and
+    // 1 - u and 2u - 1 = u - (1 - u) are multiples of 2^-24 below 1: exact.
+    const float f = __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, x, 9u));
+    const float u = f - 0x1.fffffep-1f;
+    const float v = 1.0f - u;
+    const float t = u * v;
+    const float xs = u - v;
+    // d = w - 2.5 = -ln2 (log2 t + 2) - 2.5
+    const float d = fmaf(__builtin_amdgcn_logf(t), -0x1.62e430p-1f, -0x1.f17218p+1f);
+    float g = 3.9583209598959e-08f;
+    g = fmaf(g, d, 4.851791004512052e-07f);
+    g = fmaf(g, d, -4.981194706488168e-06f);
+    g = fmaf(g, d, -6.207880232977914e-06f);
+    g = fmaf(g, d, 0.00030911510111764073f);
+    g = fmaf(g, d, -0.001773041789419949f);
+    g = fmaf(g, d, -0.00590812973678112f);
+    g = fmaf(g, d, 0.34880268573760986f);
+    g = fmaf(g, d, 2.1233136653900146f);
+    const bool tail = d >= 2.5f;   // w >= 5: 0.34% of draws
+    if (__builtin_expect(__any(tail), 0)) {
+      const float e = __builtin_amdgcn_sqrtf(d + 2.5f) - 3.071047627109653f;
+      float h = -0.0003539455065038055f;
+      h = fmaf(h, e, -4.474368324736133e-05f);
+      h = fmaf(h, e, 0.0020311614498496056f);
+      h = fmaf(h, e, -0.004341235384345055f);
+      h = fmaf(h, e, 0.006380986422300339f);
+      h = fmaf(h, e, -0.008731475099921227f);
+      h = fmaf(h, e, 0.011283238418400288f);
+      h = fmaf(h, e, 1.4183263778686523f);
+      h = fmaf(h, e, 4.107142925262451f);
+      g = tail ? h : g;
     }
-    const bool central = fabsf(q) <= 0.425f;
-    const float num = central ? nc : copysignf(nt, q);
-    const float den = central ? dc : dt;
-    return num * rcp(den);
+    return xs * g;
   }
   static __device__ __forceinline__ float expv(float x) { return __expf(x); }
   static __device__ __forceinline__ float div(float a, float b) { return a * rcp(b); }
@@ -112,6 +128,7 @@ template <> struct Num<double> {
     }
     return q < 0 ? -v : v;
   }
+  static __device__ __forceinline__ double normal_word(uint32_t x) { return normal(uniform(x)); }
   static __device__ __forceinline__ double expv(double x) { return exp(x); }
   static __device__ __forceinline__ double div(double a, double b) { return a / b; }
 };
@@ -133,6 +150,8 @@ struct Args {
   int n_work;
   uint32_t* queue;
   double2* partial;
+  uint32_t* done;        // per instance: finished tiles (zero at launch)
+  double2* result;       // per instance: (sum, sum of squares), written by the last tile's block
   T* payoff_out;
   const T* paths;
   uint32_t k0, k1;
@@ -148,6 +167,8 @@ __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlan
 // space so that uniform reads become scalar loads through the scalar cache.
 template <typename T>
 using kptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+using lptr = const __attribute__((address_space(3))) T*;
 template <typename T>
 __device__ __forceinline__ kptr<T> K(const T* p) { return (kptr<T>)p; }
 
@@ -193,12 +214,17 @@ struct GenSource {
   kptr<uint32_t> sobol;
   kptr<uint32_t> sobol_hi;   // this wave's row of the high-part table
   uint32_t gmask[6];         // -(bit b of the point's Gray code), b < 6
+  lptr<uint32_t> lo;         // LDS table of low-bit XORs, at this lane's Gray bits
+  bool use_lo;
   kptr<T> slotc;
   kptr<T> spotp;
   Model<T, A> M;
 
-  __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p) {
+  __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p, lptr<uint32_t> lo_tab,
+                                       bool has_lo) {
     path = p; gray = p ^ (p >> 1);
+    use_lo = RNG == 1 && has_lo;
+    lo = lo_tab + (gray & 63u);
     k0 = g.k0; k1 = g.k1; inst = d.instance;
     n_slots = d.n_slots; sobol_bits = g.sobol_bits; sobol = K(g.sobol);
     sobol_dims = g.sobol_dims;
@@ -243,14 +269,29 @@ struct GenSource {
     }
   }
 
+  // the A words of slot q (words q*A .. q*A+A-1); the table case issues its
+  // A loads together
+  __device__ __forceinline__ void words(int q, uint32_t (&xw)[A]) {
+    const uint32_t w0 = (uint32_t)(q * A);
+    if (RNG == 1 && use_lo) {
+#pragma unroll
+      for (int a = 0; a < A; ++a) xw[a] = sobol_hi[w0 + a] ^ lo[(w0 + a) * 64u];
+    } else {
+#pragma unroll
+      for (int a = 0; a < A; ++a) xw[a] = word(w0 + a);
+    }
+  }
+
   // one GBM step to slot q (all assets); optionally record words/normals
   __device__ __forceinline__ void step(int q, uint32_t* wout, T* zout, uint32_t npath) {
     T z[A];
+    uint32_t xw[A];
+    words(q, xw);
 #pragma unroll
     for (int a = 0; a < A; ++a) {
       const uint32_t w = (uint32_t)(q * A + a);
-      const uint32_t x32 = word(w);
-      z[a] = Num<T>::normal(Num<T>::uniform(x32));
+      const uint32_t x32 = xw[a];
+      z[a] = Num<T>::normal_word(x32);
       if (wout) wout[(size_t)w * npath + path] = x32;
       if (zout) zout[(size_t)w * npath + path] = z[a];
     }
@@ -289,6 +330,29 @@ struct GenSource {
   }
   __device__ __forceinline__ T spot(int a) const { return spotp[a]; }
 };
+
+// Sobol words of a wave's 64 points differ only in Gray-code bits 0..5 (bit 5
+// also takes bit 6 of the point index): entry [w][b] of the block's LDS table
+// is the XOR of dimension w's direction numbers selected by the bits of b, so
+// a word is the wave's high part XOR one table read (64 distinct entries per
+// wave: no bank conflicts).  Built by the whole block; false if the
+// dimensions do not fit.
+constexpr int kSobolLdsDims = 64;
+
+template <typename T>
+__device__ __forceinline__ bool sobol_lo_table(const Args<T>& g, uint32_t* tab) {
+  if (!g.sobol_hi || g.sobol_dims > kSobolLdsDims) return false;
+  for (int i = threadIdx.x; i < g.sobol_dims * 64; i += blockDim.x) {
+    const uint32_t* v = g.sobol + (size_t)(i >> 6) * 32u;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+      if ((i >> b) & 1) acc ^= v[b];
+    tab[i] = acc;
+  }
+  __syncthreads();
+  return true;
+}
 
 // Reads stored prices [slot][asset][path] through the same window.
 template <typename T, int A>
@@ -479,7 +543,15 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
   __shared__ double red[8];
   __shared__ int frames_all[4][3 * kMaxLoopDepth];
   __shared__ int item_s;
+  __shared__ int last_s;
   int* frames = frames_all[threadIdx.x >> 6];
+  bool has_lo = false;
+  lptr<uint32_t> lo_tab = nullptr;
+  if constexpr (RNG == 1 && !MEM) {
+    __shared__ uint32_t sob_lo[kSobolLdsDims * 64];
+    has_lo = sobol_lo_table(g, sob_lo);
+    lo_tab = (lptr<uint32_t>)sob_lo;
+  }
   int item = blockIdx.x;
   for (;;) {
     if (g.queue) {
@@ -505,7 +577,7 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
         v = Eval::template run<T>(g, D, src, frames);
       } else {
         GenSource<T, RNG, A> src;
-        src.init(g, D, p);
+        src.init(g, D, p, lo_tab, has_lo);
         v = Eval::template run<T>(g, D, src, frames);
       }
       if (valid) {
@@ -515,7 +587,28 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
       }
     }
     block_sum2(s, ss, red);
-    if (threadIdx.x == 0) g.partial[D.first_item + wi.y] = make_double2(s, ss);
+    // Publish the tile's partial; the block that completes an instance's
+    // last tile sums all its partials in tile order (deterministic whichever
+    // block is last) and writes the instance's result.
+    if (threadIdx.x == 0) {
+      g.partial[D.first_item + wi.y] = make_double2(s, ss);
+      __threadfence();
+      last_s = atomicAdd(&g.done[wi.x], 1u) == D.n_tiles - 1u;
+    }
+    __syncthreads();
+    if (last_s) {
+      __threadfence();
+      double a = 0.0, b = 0.0;
+      for (uint32_t i = threadIdx.x; i < D.n_tiles; i += blockDim.x) {
+        const double2 q = g.partial[D.first_item + i];
+        a += q.x; b += q.y;
+      }
+      block_sum2(a, b, red);
+      if (threadIdx.x == 0) {
+        g.result[wi.x] = make_double2(a, b);
+        __threadfence_system();
+      }
+    }
     if (!g.queue) break;
   }
 }
@@ -523,11 +616,18 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
 // Two-phase path generation: stored prices [slot][asset][path].
 template <typename T, int RNG, int A>
 __device__ __forceinline__ void pathgen_body(const Args<T>& g, T* out, uint32_t* wout, T* zout, uint32_t n_paths) {
+  bool has_lo = false;
+  lptr<uint32_t> lo_tab = nullptr;
+  if constexpr (RNG == 1) {
+    __shared__ uint32_t sob_lo[kSobolLdsDims * 64];
+    has_lo = sobol_lo_table(g, sob_lo);
+    lo_tab = (lptr<uint32_t>)sob_lo;
+  }
   const uint32_t path = blockIdx.x * blockDim.x + threadIdx.x;
   if (path >= n_paths) return;
   const InstDesc D = load_desc(g.desc, 0);
   GenSource<T, RNG, A> src;
-  src.init(g, D, path);
+  src.init(g, D, path, lo_tab, has_lo);
   for (int q = 0; q < D.n_slots; ++q) {
     src.step(q, wout, zout, n_paths);
 #pragma unroll
@@ -535,9 +635,6 @@ __device__ __forceinline__ void pathgen_body(const Args<T>& g, T* out, uint32_t*
       out[((size_t)q * A + a) * n_paths + path] = src.M.s0[a] * Num<T>::expv(src.x[a]);
   }
 }
-
-// Deterministic per-instance sum of the work-item partials: one block per
-// instance, fixed summation order.
 
 }  // namespace eng
 }  // namespace pmc

@@ -12,6 +12,8 @@
 // GBM steps) or by loading stored prices [slot][asset][path].
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 #include "mc_engine.h"
 
@@ -25,6 +27,7 @@ Args<T> typed(const McLaunch& a) {
   g.code = a.code; g.consts = (const T*)a.consts; g.desc = a.desc; g.itab = a.itab;
   g.rtab = (const T*)a.rtab; g.chol = a.chol; g.sobol = a.sobol; g.sobol_bits = a.sobol_bits;
   g.order = a.order; g.tiles = a.tiles; g.n_work = a.n_work; g.queue = a.queue; g.partial = a.partial;
+  g.done = a.done; g.result = a.result;
   g.payoff_out = (T*)a.payoff_out; g.paths = (const T*)a.paths; g.k0 = a.k0; g.k1 = a.k1;
   g.ppt = a.ppt; g.n_assets = a.n_assets;
   g.sobol_hi = a.sobol_hi; g.sobol_dims = a.sobol_dims;
@@ -41,21 +44,13 @@ __global__ __launch_bounds__(256) void k_pathgen(Args<T> g, T* out, uint32_t* wo
   pathgen_body<T, RNG, A>(g, out, wout, zout, n_paths);
 }
 
-__global__ __launch_bounds__(256) void k_reduce(const double2* partial, const InstDesc* desc, double2* out) {
-  __shared__ double red[8];
-  const InstDesc& D = desc[blockIdx.x];
-  double s = 0.0, ss = 0.0;
-  for (uint32_t i = threadIdx.x; i < D.n_tiles; i += blockDim.x) {
-    const double2 p = partial[D.first_item + i];
-    s += p.x; ss += p.y;
-  }
-  block_sum2(s, ss, red);
-  if (threadIdx.x == 0) out[blockIdx.x] = make_double2(s, ss);
-}
-
-// FP64 Cholesky-Banachiewicz, one matrix per thread (m <= 4 in practice).
-__global__ void k_cholesky(const double* a, double* l, int* bad, int n, int m) {
+// Prepares a launch: zeroes n_zero work counters and factors every
+// instance's correlation matrix (FP64 Cholesky-Banachiewicz, one matrix per
+// thread).  status[i] = 0 if matrix i is positive definite, else 1.  A kernel
+// rather than a memset, so that the sequence can be captured into a graph.
+__global__ void k_prep(const double* a, double* l, int* status, uint32_t* zero, int n_zero, int n, int m) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_zero) zero[i] = 0u;
   if (i >= n) return;
   const double* A_ = a + (size_t)i * m * m;
   double* L = l + (size_t)i * m * m;
@@ -74,7 +69,8 @@ __global__ void k_cholesky(const double* a, double* l, int* bad, int n, int m) {
       }
     }
   }
-  if (!ok) atomicMin(bad, i);
+  status[i] = ok ? 0 : 1;
+  __threadfence_system();
 }
 
 __global__ void k_sobol_hi(const uint32_t* v, uint32_t* hi, int n_rows, int dims, int bits) {
@@ -86,11 +82,6 @@ __global__ void k_sobol_hi(const uint32_t* v, uint32_t* hi, int n_rows, int dims
   for (int b = 6; b < bits; ++b)
     if ((gh >> (b - 6)) & 1u) acc ^= v[d * 32u + b];
   hi[i] = acc;
-}
-
-__global__ void k_fill_u32(uint32_t* p, uint32_t v, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
 }
 
 template <typename T, int RNG, int A>
@@ -177,25 +168,16 @@ hipError_t launch_mc_jit(hipFunction_t f, int precision, const McLaunch& a, int 
   return hipModuleLaunchKernel(f, grid, 1, 1, block, 1, 1, 0, s, params, nullptr);
 }
 
-hipError_t launch_reduce(const double2* partial, const InstDesc* desc, int n_inst, double2* out,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(n_inst), dim3(256), 0, s, partial, desc, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_cholesky(const double* a, double* l, int* bad, int n, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_cholesky, dim3((n + 255) / 256), dim3(256), 0, s, a, l, bad, n, m);
+hipError_t launch_prep(const double* a, double* l, int* status, uint32_t* zero, int n_zero, int n, int m,
+                       hipStream_t s) {
+  const int t = std::max(n, n_zero);
+  hipLaunchKernelGGL(k_prep, dim3((t + 255) / 256), dim3(256), 0, s, a, l, status, zero, n_zero, n, m);
   return hipGetLastError();
 }
 
 hipError_t launch_sobol_hi(const uint32_t* sobol, uint32_t* hi, int n_rows, int dims, int bits, hipStream_t s) {
   const int n = n_rows * dims;
   hipLaunchKernelGGL(k_sobol_hi, dim3((n + 255) / 256), dim3(256), 0, s, sobol, hi, n_rows, dims, bits);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
   return hipGetLastError();
 }
 
@@ -206,6 +188,12 @@ int mc_occupancy(int precision, int rng, int n_assets, int n_regs, int block) {
   if (precision == 1) { if (rng) { OCC(double, 1) } else { OCC(double, 0) } }
   if (rng) { OCC(float, 1) } else { OCC(float, 0) }
 #undef OCC
+}
+
+int mc_occupancy_jit(hipFunction_t f, int block) {
+  int n = 0;
+  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, 0) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
 }
 
 }  // namespace pmc

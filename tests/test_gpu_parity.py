@@ -307,6 +307,10 @@ def test_edge_cases_single_path_and_no_slots():
     assert r["price"] == pytest.approx(2 * math.exp(-0.03 * 10 / 252), rel=1e-12)
     r = P.price(cash, [], [], **model_kw(cfg), **opts_kw(cfg, 777, parties=("Y", "X")))
     assert r["price"] == pytest.approx(-2 * math.exp(-0.03 * 10 / 252), rel=1e-12)
+    # the same with Sobol words (no dimension is drawn) in both precisions
+    for prec in ("f64", "f32"):
+        r = P.price(cash, [], [], **model_kw(cfg), **opts_kw(cfg, 777, rng="sobol", precision=prec))
+        assert r["price"] == pytest.approx(2 * math.exp(-0.03 * 10 / 252), rel=1e-6)
 
 
 @pytest.mark.parametrize("engine", ["interpreter", "compiled"])

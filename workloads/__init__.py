@@ -49,6 +49,20 @@ DOWN_AND_OUT_CALL = """
 """
 
 
+# Forward contract: pays S_T - K at day T (linear in the spot on every path).
+FORWARD = """
+(mult (sub (model S (tvar T)) (model K 0)) (payoff (tvar T) X Y))
+"""
+
+# Two-asset basket call: pays (S1_T + S2_T)/2 - K at day T when positive.
+BASKET_CALL = """
+(if (lt (model K 0) (mult (real 0.5) (add (model S1 (tvar T)) (model S2 (tvar T)))))
+    (mult (sub (mult (real 0.5) (add (model S1 (tvar T)) (model S2 (tvar T)))) (model K 0))
+          (payoff (tvar T) X Y))
+    (real 0.0))
+"""
+
+
 def _worst(day):
     """min over the three assets on a day offset (an ILTExprZ)."""
     return f"(min (min (model S1 {day}) (model S2 {day})) (model S3 {day}))"
@@ -173,3 +187,9 @@ C5 = Config(
                                      "judge_paths": 1 << 22, "infer_batch": 65536})
 
 CONFIGS = {"C1": C1, "C2": C2, "C3": C3, "C4": C4, "C5": C5}
+
+
+# Risk workload: bump-and-revalue Greeks (delta, gamma per spot; vega per
+# volatility) of the C4 instruments by central differences on common random
+# numbers; spot bumps are relative, volatility bumps absolute.
+RISK_BUMPS = {"rel_spot_bump": 0.01, "abs_vol_bump": 0.01}
