@@ -287,6 +287,12 @@ int pmc_mlp_create(pmc_ctx* ctx, int n_in, int width, uint64_t seed, const doubl
                    const double* in_hi, double y_scale, pmc_mlp** out);
 void pmc_mlp_free(pmc_mlp* m);
 /* Number of parameters (weights and biases of all layers). */
+/* Save the network (shape, input box, y_scale and FP32 master weights) to a
+ * binary file; pmc_mlp_load re-creates it on ctx's device with fresh Adam
+ * state.  Errors: PMC_E_ARG (file cannot be opened or written), PMC_E_PARSE
+ * (not a file written by pmc_mlp_save of a supported shape). */
+int pmc_mlp_save(const pmc_mlp* m, const char* path);
+int pmc_mlp_load(pmc_ctx* ctx, const char* path, pmc_mlp** out);
 int64_t pmc_mlp_num_params(const pmc_mlp* m);
 /* Host FP32 copies of the master weights in the order W1 b1 W2 b2 W3 b3 W4 b4,
  * each W row-major [out][in]. */

@@ -114,6 +114,8 @@ _sig = {
                             C.POINTER(_vp)]),
     "pmc_mlp_free": (None, [_vp]),
     "pmc_mlp_num_params": (_i64, [_vp]),
+    "pmc_mlp_save": (_i, [_vp, C.c_char_p]),
+    "pmc_mlp_load": (_i, [_vp, C.c_char_p, C.POINTER(_vp)]),
     "pmc_mlp_get_params": (_i, [_vp, C.POINTER(C.c_float)]),
     "pmc_mlp_set_params": (_i, [_vp, C.POINTER(C.c_float)]),
     "pmc_mlp_train_epoch": (_i, [_vp, _vp, _vp, _i64, C.POINTER(TrainOpts), C.POINTER(C.c_double)]),
@@ -322,6 +324,20 @@ class Surrogate:
                                      C.byref(h)))
         self.h = h
         self.n_params = int(lib.pmc_mlp_num_params(h))
+
+    def save(self, path):
+        """Writes the network to a file (pmc_mlp_save)."""
+        self.ctx.check(lib.pmc_mlp_save(self.h, str(path).encode()))
+
+    @classmethod
+    def load(cls, ctx: Context, path):
+        """A network read back from a pmc_mlp_save file (pmc_mlp_load)."""
+        h = C.c_void_p()
+        ctx.check(lib.pmc_mlp_load(ctx.h, str(path).encode(), C.byref(h)))
+        self = cls.__new__(cls)
+        self.ctx, self.h = ctx, h
+        self.n_params = int(lib.pmc_mlp_num_params(h))
+        return self
 
     def __del__(self):
         try:

@@ -569,15 +569,16 @@ int finish(pmc_ctx* c, int n_inst, const std::vector<uint64_t>& n_paths, const s
 }
 
 // Launches the Monte Carlo kernel with the requested payoff engine.
+// lanes: paths per lane (compiled engine with stored paths only).
 int launch_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec, bool mem, const McLaunch& L,
-                  int grid, int block) {
+                  int grid, int block, int lanes = 1) {
   if (o->engine == PMC_ENGINE_INTERPRETER) {
     HIP_TRY(c, launch_mc(prec, o->rng, mem, L, grid, block, c->stream));
     return PMC_OK;
   }
   hipFunction_t f = nullptr;
   std::string err;
-  int st = p->jit.get(p->prog, c->device, prec, o->rng, (int)p->prog.assets.size(), mem, &f, err);
+  int st = p->jit.get(p->prog, c->device, prec, o->rng, (int)p->prog.assets.size(), mem, &f, err, lanes);
   if (st != PMC_OK) return fail(c, st, err);
   HIP_TRY(c, launch_mc_jit(f, prec, L, grid, block, c->stream));
   return PMC_OK;
@@ -617,7 +618,17 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
     const int64_t cost = it->second;
     mode = (cost >= 0 && cost <= 2 * (int64_t)std::max(1, n_slots)) ? PMC_MODE_FUSED : PMC_MODE_TWO_PHASE;
   }
-  const uint32_t tiles = (uint32_t)((N + block - 1) / block);
+  // The compiled evaluator of stored paths gives each lane several
+  // consecutive paths (one 16-byte load per slot) when the path count and
+  // the buffer's alignment allow it.
+  int lanes = 1;
+  if (mode == PMC_MODE_TWO_PHASE && o->engine != PMC_ENGINE_INTERPRETER && n_slots > 0) {
+    const int want = sizeof(T) == 8 ? 2 : 4;
+    const bool aligned = !given_paths || ((uintptr_t)given_paths % (want * sizeof(T))) == 0;
+    if (N % (uint64_t)want == 0 && aligned) lanes = want;
+  }
+  const uint64_t tile_paths = (uint64_t)block * (uint64_t)lanes;
+  const uint32_t tiles = (uint32_t)((N + tile_paths - 1) / tile_paths);
   tb.desc[0].n_tiles = tiles;
   tb.desc[0].first_item = 0;
   McLaunch L;
@@ -645,7 +656,7 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
     }
     if (n_slots == 0) L.paths = nullptr;
     HIP_TRY(c, hipEventRecord(c->evk[1], c->stream));
-    st = launch_engine(c, p, o, prec, n_slots > 0, L, (int)tiles, block);
+    st = launch_engine(c, p, o, prec, n_slots > 0, L, (int)tiles, block, lanes);
   } else {
     HIP_TRY(c, hipEventRecord(c->evk[1], c->stream));
     st = launch_engine(c, p, o, prec, false, L, (int)tiles, block);

@@ -19,13 +19,14 @@ namespace pmc {
 std::string generate_payoff(const Program& P);
 
 // Compiled kernels of one payoff, keyed by (device, precision, rng, assets,
-// memory source).  Owned by the payoff object.
+// memory source, paths per lane).  Owned by the payoff object.
 class JitCache {
  public:
   ~JitCache();
   // Returns the kernel for the variant, compiling it on first use.
+  // lanes > 1 (paths per lane) is for the memory source only.
   int get(const Program& P, int device, int precision, int rng, int n_assets, bool from_memory,
-          hipFunction_t* out, std::string& err);
+          hipFunction_t* out, std::string& err, int lanes = 1);
 
  private:
   std::mutex mu_;

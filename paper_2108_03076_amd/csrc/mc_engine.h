@@ -199,9 +199,141 @@ struct Model {
   }
 };
 
+// ------------------------------------------------------ lane vectors -----
+// The two-phase evaluator may give each lane P consecutive paths: the
+// generated payoff then computes on P-wide values and decisions, while its
+// wave-uniform work (loop shift and counters, day->slot lookups, window
+// management) is shared by the P paths and the stored prices of a slot come
+// in one P-wide load.  For P = 1 the types are plain T and bool and every
+// helper below is the scalar operation itself, so a compiled payoff computes
+// exactly what the interpreter computes.
+template <typename T, int P>
+struct alignas(sizeof(T) * P) LaneVec {
+  T v[P];
+  LaneVec() = default;
+  __device__ __forceinline__ LaneVec(T x) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) v[i] = x;
+  }
+};
+template <int P>
+struct LaneMask {
+  bool b[P];
+  LaneMask() = default;
+  __device__ __forceinline__ LaneMask(bool x) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) b[i] = x;
+  }
+};
+template <bool B, class X, class Y> struct pick_t { using type = X; };
+template <class X, class Y> struct pick_t<false, X, Y> { using type = Y; };
+template <typename T, int P>
+using VecT = typename pick_t<P == 1, T, LaneVec<T, P>>::type;
+template <int P>
+using MaskT = typename pick_t<P == 1, bool, LaneMask<P>>::type;
+
+template <typename T> __device__ __forceinline__ T lane_elem(T x, int) { return x; }
+template <typename T, int P> __device__ __forceinline__ T lane_elem(const LaneVec<T, P>& x, int i) { return x.v[i]; }
+
+#define PMC_VEC_BINARY(NAME, EXPR)                                                              \
+  template <typename T>                                                                         \
+  __device__ __forceinline__ T NAME(T a, T b) { return EXPR; }                                  \
+  template <typename T, int P>                                                                  \
+  __device__ __forceinline__ LaneVec<T, P> NAME(const LaneVec<T, P>& x, const LaneVec<T, P>& y) { \
+    LaneVec<T, P> r;                                                                            \
+    _Pragma("unroll") for (int i = 0; i < P; ++i) {                                             \
+      const T a = x.v[i], b = y.v[i];                                                           \
+      r.v[i] = EXPR;                                                                            \
+    }                                                                                           \
+    return r;                                                                                   \
+  }
+PMC_VEC_BINARY(vadd, a + b)
+PMC_VEC_BINARY(vsub, a - b)
+PMC_VEC_BINARY(vmul, a * b)
+PMC_VEC_BINARY(vdiv, Num<T>::div(a, b))
+PMC_VEC_BINARY(vmin, fmin(a, b))
+PMC_VEC_BINARY(vmax, fmax(a, b))
+#undef PMC_VEC_BINARY
+
+#define PMC_VEC_COMPARE(NAME, OP)                                                                   \
+  template <typename T>                                                                             \
+  __device__ __forceinline__ bool NAME(T a, T b) { return a OP b; }                                 \
+  template <typename T, int P>                                                                      \
+  __device__ __forceinline__ LaneMask<P> NAME(const LaneVec<T, P>& x, const LaneVec<T, P>& y) {     \
+    LaneMask<P> r;                                                                                  \
+    _Pragma("unroll") for (int i = 0; i < P; ++i) r.b[i] = x.v[i] OP y.v[i];                        \
+    return r;                                                                                       \
+  }
+PMC_VEC_COMPARE(vlt, <)
+PMC_VEC_COMPARE(vle, <=)
+PMC_VEC_COMPARE(veq, ==)
+#undef PMC_VEC_COMPARE
+
+template <typename T> __device__ __forceinline__ T vneg(T a) { return -a; }
+template <typename T, int P> __device__ __forceinline__ LaneVec<T, P> vneg(const LaneVec<T, P>& x) {
+  LaneVec<T, P> r;
+#pragma unroll
+  for (int i = 0; i < P; ++i) r.v[i] = -x.v[i];
+  return r;
+}
+__device__ __forceinline__ bool vnot(bool a) { return !a; }
+__device__ __forceinline__ bool vand(bool a, bool b) { return a && b; }
+__device__ __forceinline__ bool vor(bool a, bool b) { return a || b; }
+__device__ __forceinline__ bool vany(bool a) { return __any(a); }
+__device__ __forceinline__ bool vall(bool a) { return __all(a); }
+template <typename T> __device__ __forceinline__ T vsel(bool c, T a, T b) { return c ? a : b; }
+template <int P> __device__ __forceinline__ LaneMask<P> vnot(const LaneMask<P>& a) {
+  LaneMask<P> r;
+#pragma unroll
+  for (int i = 0; i < P; ++i) r.b[i] = !a.b[i];
+  return r;
+}
+template <int P> __device__ __forceinline__ LaneMask<P> vand(const LaneMask<P>& a, const LaneMask<P>& b) {
+  LaneMask<P> r;
+#pragma unroll
+  for (int i = 0; i < P; ++i) r.b[i] = a.b[i] && b.b[i];
+  return r;
+}
+template <int P> __device__ __forceinline__ LaneMask<P> vor(const LaneMask<P>& a, const LaneMask<P>& b) {
+  LaneMask<P> r;
+#pragma unroll
+  for (int i = 0; i < P; ++i) r.b[i] = a.b[i] || b.b[i];
+  return r;
+}
+template <int P> __device__ __forceinline__ bool vany(const LaneMask<P>& a) {
+  bool x = false;
+#pragma unroll
+  for (int i = 0; i < P; ++i) x = x || a.b[i];
+  return __any(x);
+}
+template <int P> __device__ __forceinline__ bool vall(const LaneMask<P>& a) {
+  bool x = true;
+#pragma unroll
+  for (int i = 0; i < P; ++i) x = x && a.b[i];
+  return __all(x);
+}
+template <typename T, int P>
+__device__ __forceinline__ LaneVec<T, P> vsel(const LaneMask<P>& c, const LaneVec<T, P>& a, const LaneVec<T, P>& b) {
+  LaneVec<T, P> r;
+#pragma unroll
+  for (int i = 0; i < P; ++i) r.v[i] = c.b[i] ? a.v[i] : b.v[i];
+  return r;
+}
+template <int P>
+__device__ __forceinline__ LaneMask<P> vsel(const LaneMask<P>& c, const LaneMask<P>& a, const LaneMask<P>& b) {
+  LaneMask<P> r;
+#pragma unroll
+  for (int i = 0; i < P; ++i) r.b[i] = c.b[i] ? a.b[i] : b.b[i];
+  return r;
+}
+
 // Generates the path of one lane slot by slot into the window.
 template <typename T, int RNG, int A>
 struct GenSource {
+  using V = T;
+  using Mask = bool;
+  static constexpr int kWin = kWindow;
+  using Win = T[kWindow];
   static constexpr int WS = kWindow / A;   // slots held in the window
   T x[A];
   int base;        // first slot in the window (uniform), -1 if empty
@@ -354,9 +486,15 @@ __device__ __forceinline__ bool sobol_lo_table(const Args<T>& g, uint32_t* tab) 
   return true;
 }
 
-// Reads stored prices [slot][asset][path] through the same window.
+// Reads stored prices [slot][asset][path] through the same kind of window;
+// with P > 1 a lane holds paths path .. path+P-1 (path a multiple of P, the
+// path count a multiple of P) and each entry is one P-wide load.
 template <typename T, int A>
 struct MemSource {
+  using V = T;
+  using Mask = bool;
+  static constexpr int kWin = kWindow;
+  using Win = T[kWindow];
   static constexpr int WS = kWindow / A;
   int base, n_slots;
   uint32_t path, n_paths;
@@ -369,7 +507,7 @@ struct MemSource {
     spotp = K(g.rtab) + d.model_off + 2 * A;
   }
   // Loads slots s .. s+WS-1 (clamped) with WS * A independent loads.
-  __device__ __forceinline__ void refill(T (&win)[kWindow], int s) {
+  __device__ __forceinline__ void refill(Win& win, int s) {
     const int last = n_slots - 1;
 #pragma unroll
     for (int j = 0; j < WS; ++j) {
@@ -380,7 +518,7 @@ struct MemSource {
     }
     base = s;
   }
-  __device__ __forceinline__ T read(T (&win)[kWindow], int slot, int a) {
+  __device__ __forceinline__ T read(Win& win, int slot, int a) {
     if (slot < base || slot >= base + WS || base < 0) refill(win, slot);
     const int i = uni((slot - base) * A + a) & (kWindow - 1);
     return win[i];
@@ -388,11 +526,67 @@ struct MemSource {
   __device__ __forceinline__ T spot(int a) const { return spotp[a]; }
 };
 
+// The same with P consecutive paths per lane (path a multiple of P, the path
+// count a multiple of P): each window entry is one P-wide load, and the
+// window lives in LDS laid out [entry][thread] so that a wave reads or
+// writes one contiguous 64 * P * sizeof(T) bytes (no bank conflicts, and no
+// register copies of a loop-carried window).
+template <typename T>
+using lwptr = __attribute__((address_space(3))) T*;
+constexpr int kLdsWin = 8;   // window entries per lane
+
+template <typename T, int A, int P>
+struct MemSourceLds {
+  using V = LaneVec<T, P>;
+  using Mask = LaneMask<P>;
+  static constexpr int kWin = kLdsWin;
+  using Win = char[1];       // the window is in LDS
+  static constexpr int WS = kLdsWin / A;
+  int base, n_slots, stride;
+  uint32_t path, n_paths;
+  const T* paths;
+  lwptr<T> lw;               // this lane's entry 0; entry i at lw + i * stride
+  kptr<T> spotp;
+
+  __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p, lwptr<T> lds) {
+    path = p; n_paths = d.n_paths; n_slots = d.n_slots; base = -1;
+    paths = g.paths;
+    stride = (int)blockDim.x * P;
+    lw = lds + threadIdx.x * P;
+    spotp = K(g.rtab) + d.model_off + 2 * A;
+  }
+  __device__ __forceinline__ void refill(int s) {
+    const int last = n_slots - 1;
+    V x[WS * A];
+#pragma unroll
+    for (int j = 0; j < WS; ++j) {
+      const int q = min(s + j, last);
+#pragma unroll
+      for (int a = 0; a < A; ++a)
+        x[j * A + a] = *reinterpret_cast<const V*>(paths + ((size_t)q * A + a) * n_paths + path);
+    }
+#pragma unroll
+    for (int i = 0; i < WS * A; ++i)
+#pragma unroll
+      for (int e = 0; e < P; ++e) lw[i * stride + e] = x[i].v[e];
+    base = s;
+  }
+  __device__ __forceinline__ V read(Win&, int slot, int a) {
+    if (slot < base || slot >= base + WS || base < 0) refill(slot);
+    const int i = uni((slot - base) * A + a);
+    V r;
+#pragma unroll
+    for (int e = 0; e < P; ++e) r.v[e] = lw[i * stride + e];
+    return r;
+  }
+  __device__ __forceinline__ V spot(int a) const { return V(spotp[a]); }
+};
+
 // An observable of a model asset on a day: the spot for day <= 0 (flat
 // history), else the simulated price of the day's slot.
-template <typename T, class Src>
-__device__ __forceinline__ T read_obs(Src& src, T (&win)[kWindow], const InstDesc& D, kptr<int32_t> dm, int day,
-                                      int asset) {
+template <class Src>
+__device__ __forceinline__ typename Src::V read_obs(Src& src, typename Src::Win& win, const InstDesc& D,
+                                                    kptr<int32_t> dm, int day, int asset) {
   if (day <= 0) return src.spot(asset);
   const int s = D.dense_first > 0 ? min(day - D.dense_first, D.n_slots - 1) : uni(dm[min(day, D.horizon)]);
   return s < 0 ? src.spot(asset) : src.read(win, s, asset);
@@ -538,8 +732,11 @@ struct Interp {
   }
 };
 
-template <typename T, int RNG, int A, bool MEM, class Eval>
+// P > 1 (two-phase only): each lane evaluates P consecutive paths; a tile
+// is then P * blockDim paths.
+template <typename T, int RNG, int A, bool MEM, class Eval, int P = 1>
 __device__ __forceinline__ void mc_body(const Args<T>& g) {
+  static_assert(P == 1 || MEM, "several paths per lane are for stored paths only");
   __shared__ double red[8];
   __shared__ int frames_all[4][3 * kMaxLoopDepth];
   __shared__ int item_s;
@@ -551,6 +748,11 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
     __shared__ uint32_t sob_lo[kSobolLdsDims * 64];
     has_lo = sobol_lo_table(g, sob_lo);
     lo_tab = (lptr<uint32_t>)sob_lo;
+  }
+  lwptr<T> mem_win = nullptr;
+  if constexpr (MEM && P > 1) {
+    __shared__ __align__(16) T win_lds[kLdsWin * 256 * P];   // [entry][thread][P], blockDim <= 256
+    mem_win = (lwptr<T>)win_lds;
   }
   int item = blockIdx.x;
   for (;;) {
@@ -567,11 +769,14 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
     const InstDesc D = load_desc(g.desc, wi.x);
     double s = 0.0, ss = 0.0;
     for (int r = 0; r < g.ppt; ++r) {
-      const uint32_t path = ((uint32_t)wi.y * (uint32_t)g.ppt + (uint32_t)r) * blockDim.x + threadIdx.x;
-      const bool valid = path < D.n_paths;
-      const uint32_t p = valid ? path : D.n_paths - 1;
-      T v;
-      if (MEM) {
+      const uint32_t path0 = (((uint32_t)wi.y * (uint32_t)g.ppt + (uint32_t)r) * blockDim.x + threadIdx.x) * P;
+      const uint32_t p = path0 < D.n_paths ? path0 : D.n_paths - P;
+      VecT<T, P> v;
+      if constexpr (MEM && P > 1) {
+        MemSourceLds<T, A, P> src;
+        src.init(g, D, p, mem_win);
+        v = Eval::template run<T>(g, D, src, frames);
+      } else if constexpr (MEM) {
         MemSource<T, A> src;
         src.init(g, D, p);
         v = Eval::template run<T>(g, D, src, frames);
@@ -580,10 +785,15 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
         src.init(g, D, p, lo_tab, has_lo);
         v = Eval::template run<T>(g, D, src, frames);
       }
-      if (valid) {
-        const double x = (double)v;
-        s += x; ss += x * x;
-        if (g.payoff_out) g.payoff_out[path] = v;
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        const uint32_t path = path0 + (uint32_t)e;
+        if (path < D.n_paths) {
+          const T ve = lane_elem(v, e);
+          const double x = (double)ve;
+          s += x; ss += x * x;
+          if (g.payoff_out) g.payoff_out[path] = ve;
+        }
       }
     }
     block_sum2(s, ss, red);

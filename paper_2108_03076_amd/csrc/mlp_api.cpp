@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -40,6 +41,7 @@ struct pmc_mlp {
   pmc_ctx* ctx = nullptr;
   int n_in = 8, width = 256;
   double y_scale = 100.0;
+  std::vector<double> lo, hi;   // the input box (host copy, for saving)
   int64_t n_params = 0;
   int64_t step = 0;
   // flat parameter offsets
@@ -172,6 +174,8 @@ extern "C" int pmc_mlp_create(pmc_ctx* ctx, int n_in, int width, uint64_t seed, 
   M->n_in = n_in;
   M->width = width;
   M->y_scale = y_scale;
+  M->lo.assign(in_lo, in_lo + n_in);
+  M->hi.assign(in_hi, in_hi + n_in);
   const int W = width;
   const int outs[4] = {W, W, W, 1}, ins[4] = {n_in, W, W, W};
   int64_t off = 0;
@@ -323,5 +327,68 @@ extern "C" int pmc_mlp_train_epoch(pmc_mlp* m, const float* x, const float* y, i
   MLP_TRY(m, hipMemcpyAsync(&acc, m->loss_acc.p, 8, hipMemcpyDeviceToHost, s));
   MLP_TRY(m, hipStreamSynchronize(s));
   if (mean_loss) *mean_loss = acc / (double)(steps * B);
+  return PMC_OK;
+}
+
+// File layout (native byte order): the 8 bytes "PMCMLP1\n", int32 n_in,
+// int32 width, float64 y_scale, float64 lo[n_in], float64 hi[n_in],
+// int64 n_params, float32 master weights [n_params] (W1 b1 .. W4 b4).
+static const char kMlpMagic[8] = {'P', 'M', 'C', 'M', 'L', 'P', '1', '\n'};
+
+extern "C" int pmc_mlp_save(const pmc_mlp* m, const char* path) {
+  if (!m || !path) return PMC_E_ARG;
+  std::vector<float> w((size_t)m->n_params);
+  int rc = pmc_mlp_get_params(m, w.data());
+  if (rc != PMC_OK) return rc;
+  pmc_mlp* M = const_cast<pmc_mlp*>(m);
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return ctx_fail(M->ctx, PMC_E_ARG, std::string("cannot open ") + path + " for writing");
+  const int32_t n_in = m->n_in, width = m->width;
+  const int64_t np = m->n_params;
+  bool ok = std::fwrite(kMlpMagic, 1, 8, f) == 8 && std::fwrite(&n_in, 4, 1, f) == 1 &&
+            std::fwrite(&width, 4, 1, f) == 1 && std::fwrite(&m->y_scale, 8, 1, f) == 1 &&
+            std::fwrite(m->lo.data(), 8, n_in, f) == (size_t)n_in &&
+            std::fwrite(m->hi.data(), 8, n_in, f) == (size_t)n_in && std::fwrite(&np, 8, 1, f) == 1 &&
+            std::fwrite(w.data(), 4, w.size(), f) == w.size();
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return ctx_fail(M->ctx, PMC_E_ARG, std::string("write failed: ") + path);
+  return PMC_OK;
+}
+
+extern "C" int pmc_mlp_load(pmc_ctx* ctx, const char* path, pmc_mlp** out) {
+  if (!ctx || !path || !out) return PMC_E_ARG;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return ctx_fail(ctx, PMC_E_ARG, std::string("cannot open ") + path);
+  char magic[8];
+  int32_t n_in = 0, width = 0;
+  double y_scale = 0;
+  int64_t np = -1;
+  std::vector<double> lo, hi;
+  std::vector<float> w;
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMlpMagic, 8) == 0 &&
+            std::fread(&n_in, 4, 1, f) == 1 && std::fread(&width, 4, 1, f) == 1 &&
+            std::fread(&y_scale, 8, 1, f) == 1 && n_in >= 1 && n_in <= 16 && width >= 32 && width <= 1024;
+  if (ok) {
+    lo.resize(n_in);
+    hi.resize(n_in);
+    ok = std::fread(lo.data(), 8, n_in, f) == (size_t)n_in && std::fread(hi.data(), 8, n_in, f) == (size_t)n_in &&
+         std::fread(&np, 8, 1, f) == 1;
+  }
+  const int64_t want = (int64_t)width * n_in + width + 2 * ((int64_t)width * width + width) + width + 1;
+  if (ok) ok = np == want;
+  if (ok) {
+    w.resize((size_t)np);
+    ok = std::fread(w.data(), 4, w.size(), f) == w.size();
+    char extra;
+    ok = ok && std::fread(&extra, 1, 1, f) == 0;   // nothing after the weights
+  }
+  std::fclose(f);
+  if (!ok) return ctx_fail(ctx, PMC_E_PARSE, std::string("not a surrogate file of this library: ") + path);
+  pmc_mlp* m = nullptr;
+  int rc = pmc_mlp_create(ctx, n_in, width, 0, lo.data(), hi.data(), y_scale, &m);
+  if (rc != PMC_OK) return rc;
+  rc = pmc_mlp_set_params(m, w.data());
+  if (rc != PMC_OK) { pmc_mlp_free(m); return rc; }
+  *out = m;
   return PMC_OK;
 }

@@ -108,3 +108,26 @@ def test_surrogate_workflow_small():
     err = S.errors(pred.cpu().numpy(), yte)
     const = S.errors(np.full(256, ytr.mean()), yte)
     assert err["rms"] < 0.25 * const["rms"], (err, const)
+
+
+def test_save_load_round_trip(tmp_path):
+    """A saved network loads back with the same weights and the same
+    inference output; a damaged file is refused."""
+    import paper_2108_03076_amd as P
+    sur = _net(seed=5)
+    f = tmp_path / "net.pmcmlp"
+    sur.save(f)
+    back = P.Surrogate.load(ctx(), f)
+    assert np.array_equal(back.get_params(), sur.get_params())
+    x, _ = _data(300, 4)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    a = torch.empty(300, dtype=torch.float32, device="cuda")
+    b = torch.empty(300, dtype=torch.float32, device="cuda")
+    sur.infer(xt, a)
+    back.infer(xt, b)
+    assert torch.equal(a, b)
+    raw = f.read_bytes()
+    bad = tmp_path / "bad.pmcmlp"
+    bad.write_bytes(raw[:-4])
+    with pytest.raises(P.PmcError):
+        P.Surrogate.load(ctx(), bad)
