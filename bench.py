@@ -185,6 +185,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only, no CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate workload")
+    ap.add_argument("--only", default="",
+                    help="comma-separated subset of the extra workloads to run (C1, C2i, C3, C4, risk, C5); "
+                         "the headline always runs")
     ap.add_argument("--surrogate-points", type=int, default=1 << 20,
                     help="training points of the surrogate (each priced by Monte Carlo with 2^16 paths)")
     ap.add_argument("--surrogate-epochs", type=int, default=60)
@@ -261,7 +264,9 @@ def main():
     }
 
     extra = {}
-    if not args.quick:
+    only = set(x.strip() for x in args.only.split(",") if x.strip())
+    want = lambda name: not args.quick and (not only or name in only)
+    if want("C1"):
         # C1: FP64 European call (latency-bound at 2^16 paths)
         c1 = W.C1
         pay1, kw1 = setup(c1)
@@ -269,12 +274,14 @@ def main():
         extra["C1_fp64_european"] = {"ms_per_step": s1 * 1e3, "path_dates_per_s": c1.n_paths / s1,
                                      "kernel_ms": float(np.mean([o["eval_ms"] for o in o1])),
                                      "price": o1[-1]["price"], "std_err": o1[-1]["std_err"]}
+    if want("C2i"):
         # the headline workload with the bytecode interpreter instead of the
         # compiled payoff
         si, oi = time_steps(lambda: P.price(pay2, c2.tenv, c2.params, engine="interpreter", **kw2),
                             max(3, args.steps // 4), 1)
         extra["C2_interpreter"] = {"ms_per_step": si * 1e3, "path_dates_per_s": pd / si,
                                    "kernel_ms": float(np.mean([o["eval_ms"] for o in oi]))}
+    if want("C3"):
         # C3: 1260-day down-and-out call, fused and two-phase
         c3 = W.C3
         pay3, kw3 = setup(c3)
@@ -294,6 +301,7 @@ def main():
                 gen_gbs = 4.0 * pd3 / (rec["gen_ms"] * 1e-3) / 1e9
                 rec["gen_write_GBs"] = gen_gbs
             extra[f"C3_down_and_out_{mode}_{engine}"] = rec
+    if want("C4") or want("risk"):
         # C4: 1024 templated instances, one persistent launch from a graph
         c4 = W.C4
         pay4, kw4 = setup(c4)
@@ -301,28 +309,30 @@ def main():
         tenv = T.reshape(-1, 1)
         params = np.stack([K, B], 1)
         bl, ppt = P.autotune_batch(pay4, tenv, params, **kw4)
+    if want("C4"):
         s4, o4 = time_steps(lambda: P.price_batch(pay4, tenv, params, **kw4), max(3, args.steps // 4), 1)
         pd4 = int(sum(r["path_dates"] for r in o4[-1]))
         extra["C4_batched_1024"] = {"ms_per_step": s4 * 1e3, "path_dates_per_s": pd4 / s4,
                                     "graph_ms": float(np.mean([r[0]["ms"] for r in o4])),
                                     "path_dates": pd4, "tuned_block": bl, "tuned_paths_per_thread": ppt}
+    if want("risk"):
         # Risk: delta, gamma and vega of the same 1024 instruments by central
         # differences on common random numbers, 1 + 4A = 5 scenarios each in
         # one persistent launch
         bumps = W.RISK_BUMPS
         sr, orr = time_steps(lambda: P.risk_batch(pay4, tenv, params, **bumps, **kw4), max(2, args.steps // 10), 1)
         n_scen = 1024 * 5
-        pd_r = n_scen // 1024 * pd4
+        pd_r = int(sum(r["path_dates"] for r in P.price_batch(pay4, tenv, params, **kw4))) * 5
         extra["C4_risk_1024x5"] = {"ms_per_step": sr * 1e3, "pricings_per_s": n_scen / sr,
                                    "greeks_per_s": 3 * 1024 / sr, "path_dates_per_s": pd_r / sr,
                                    "graph_ms": float(np.mean([r[0]["ms"] for r in orr])),
                                    "bumps": bumps, "instrument_0": orr[-1][0]}
-    if not args.quick and not args.no_surrogate:
+    if want("C5") and not args.no_surrogate:
         extra["C5_surrogate"] = surrogate_workload(ctx, args)
     line["workloads"] = extra
 
     if not args.quick and not args.no_cpu_baseline:
-        n_cpu = 1 << 18
+        n_cpu = 1 << 20
         v, dt = cpu_baseline(c2, n_cpu)
         line["cpu_baseline"] = {"value": v, "unit": "path-dates/s", "cores": 1, "kind": "oracle",
                                 "sample": f"first {n_cpu} of the 2^20 Sobol paths of the headline workload "

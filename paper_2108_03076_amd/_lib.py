@@ -19,6 +19,14 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                       "(or python paper_2108_03076_amd/build.py)")
 
+# torch (the source of device buffers and streams) ships its own HIP runtime;
+# load it first so that the library binds to that same runtime instead of
+# initialising a second one in the process (which then finds no device).
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 lib = C.CDLL(LIB_PATH)
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_PARSE", -3: "E_TYPE", -4: "E_TENV", -5: "E_HORIZON",
@@ -162,7 +170,8 @@ class Context:
         h = C.c_void_p()
         st = lib.pmc_ctx_create(int(device), C.c_void_p(stream), C.byref(h))
         if st != 0:
-            raise PmcError(st, "pmc_ctx_create failed")
+            msg = lib.pmc_last_error(None)
+            raise PmcError(st, "pmc_ctx_create failed: " + (msg.decode() if msg else ""))
         self.h = h
         self._keep = []
 

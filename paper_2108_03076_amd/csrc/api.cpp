@@ -95,6 +95,7 @@ struct pmc_ctx {
   std::string device_name;
   GraphCache graph;
   std::map<std::string, std::pair<int, int>> tuned;  // batch shape -> (block, ppt)
+  std::map<std::string, int> occupancy;   // kernel variant and block size -> resident blocks per CU
 };
 
 struct pmc_payoff {
@@ -131,20 +132,27 @@ int ctx_fail(pmc_ctx* c, int status, const std::string& msg) { return fail(c, st
 extern "C" const char* pmc_version(void) { return "pmc 1.0 (gfx950)"; }
 
 extern "C" int pmc_ctx_create(int device, void* stream, pmc_ctx** out) {
-  if (!out) return PMC_E_ARG;
+  if (!out) return fail(nullptr, PMC_E_ARG, "null out");
+  auto hip_fail = [](const char* what, hipError_t e) {
+    return fail(nullptr, PMC_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  };
   int n = 0;
-  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return PMC_E_HIP;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail("hipGetDeviceCount", e);
+  if (device < 0 || device >= n)
+    return fail(nullptr, PMC_E_ARG, "device " + std::to_string(device) + " of " + std::to_string(n));
   auto c = std::make_unique<pmc_ctx>();
   c->device = device;
   c->stream = (hipStream_t)stream;
-  if (hipSetDevice(device) != hipSuccess) return PMC_E_HIP;
+  if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail("hipSetDevice", e);
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return PMC_E_HIP;
+  if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail("hipGetDeviceProperties", e);
   c->n_cu = prop.multiProcessorCount;
   c->device_name = prop.gcnArchName;
-  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) return PMC_E_HIP;
-  for (auto& e : c->evk)
-    if (hipEventCreate(&e) != hipSuccess) return PMC_E_HIP;
+  if ((e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess)
+    return hip_fail("hipEventCreate", e);
+  for (auto& ev : c->evk)
+    if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail("hipEventCreate", e);
   *out = c.release();
   return PMC_OK;
 }
@@ -569,17 +577,36 @@ int finish(pmc_ctx* c, int n_inst, const std::vector<uint64_t>& n_paths, const s
 }
 
 // Launches the Monte Carlo kernel with the requested payoff engine.
-// lanes: paths per lane (compiled engine with stored paths only).
+// lanes: paths per lane (compiled engine with stored paths only).  Without a
+// work queue the kernel strides over the items, and the grid is capped at
+// the blocks that fit on the chip at once.
 int launch_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec, bool mem, const McLaunch& L,
                   int grid, int block, int lanes = 1) {
+  const int A = (int)p->prog.assets.size();
   if (o->engine == PMC_ENGINE_INTERPRETER) {
+    if (!L.queue) {
+      const std::string key = "interp/" + std::to_string(prec) + "/" + std::to_string(o->rng) + "/" +
+                              std::to_string(A) + "/" + std::to_string(p->prog.n_regs <= 7 ? 8 : 32) + "/" +
+                              std::to_string(block);
+      auto it = c->occupancy.find(key);
+      if (it == c->occupancy.end()) it = c->occupancy.emplace(key, mc_occupancy(prec, o->rng, A, p->prog.n_regs, block)).first;
+      grid = std::max(1, std::min(grid, c->n_cu * it->second));
+    }
     HIP_TRY(c, launch_mc(prec, o->rng, mem, L, grid, block, c->stream));
     return PMC_OK;
   }
   hipFunction_t f = nullptr;
   std::string err;
-  int st = p->jit.get(p->prog, c->device, prec, o->rng, (int)p->prog.assets.size(), mem, &f, err, lanes);
+  int st = p->jit.get(p->prog, c->device, prec, o->rng, A, mem, &f, err, lanes);
   if (st != PMC_OK) return fail(c, st, err);
+  if (!L.queue) {
+    char kb[64];
+    std::snprintf(kb, sizeof kb, "jit/%p/%d", (const void*)f, block);
+    const std::string key = kb;
+    auto it = c->occupancy.find(key);
+    if (it == c->occupancy.end()) it = c->occupancy.emplace(key, mc_occupancy_jit(f, block)).first;
+    grid = std::max(1, std::min(grid, c->n_cu * it->second));
+  }
   HIP_TRY(c, launch_mc_jit(f, prec, L, grid, block, c->stream));
   return PMC_OK;
 }

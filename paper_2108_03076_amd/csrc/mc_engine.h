@@ -338,14 +338,13 @@ struct GenSource {
   T x[A];
   int base;        // first slot in the window (uniform), -1 if empty
   int next_slot;   // next slot to generate (uniform)
-  uint32_t blk;    // Philox block held in buf (uniform)
-  uint32_t buf[4];
+  uint32_t blk;    // Philox block held in buf0..buf3 (uniform)
+  uint32_t buf0, buf1, buf2, buf3;
   uint32_t path, gray;
   uint32_t k0, k1, inst;
   int n_slots, sobol_bits, sobol_dims;
   kptr<uint32_t> sobol;
   kptr<uint32_t> sobol_hi;   // this wave's row of the high-part table
-  uint32_t gmask[6];         // -(bit b of the point's Gray code), b < 6
   lptr<uint32_t> lo;         // LDS table of low-bit XORs, at this lane's Gray bits
   bool use_lo;
   kptr<T> slotc;
@@ -367,8 +366,6 @@ struct GenSource {
       // per-wave table entry, and only bits 0..5 remain per lane.
       const uint32_t h = (uint32_t)uni((int)(p >> 6));
       sobol_hi = K(g.sobol_hi) + (size_t)h * (size_t)sobol_dims;
-#pragma unroll
-      for (int b = 0; b < 6; ++b) gmask[b] = 0u - ((gray >> b) & 1u);
     }
     M.load(g, d);
     slotc = K(g.rtab) + d.slot_off;
@@ -382,17 +379,23 @@ struct GenSource {
     if (RNG == 0) {
       const uint32_t b = w >> 2;
       if (b != blk) {
-        philox4x32_10(path, b, inst, 0u, k0, k1, buf);
+        uint32_t o[4];
+        philox4x32_10(path, b, inst, 0u, k0, k1, o);
+        buf0 = o[0]; buf1 = o[1]; buf2 = o[2]; buf3 = o[3];
         blk = b;
       }
+      // four named registers and a select (an indexed array would be
+      // demoted to scratch memory)
       const uint32_t j = w & 3u;
-      return j == 0 ? buf[0] : j == 1 ? buf[1] : j == 2 ? buf[2] : buf[3];
+      const uint32_t lo2 = (j & 1u) ? buf1 : buf0;
+      const uint32_t hi2 = (j & 1u) ? buf3 : buf2;
+      return (j & 2u) ? hi2 : lo2;
     } else {
       kptr<uint32_t> v = sobol + (size_t)w * 32u;
       if (sobol_hi) {
         uint32_t acc = sobol_hi[w];
 #pragma unroll
-        for (int b = 0; b < 6; ++b) acc ^= v[b] & gmask[b];
+        for (int b = 0; b < 6; ++b) acc ^= v[b] & (0u - ((gray >> b) & 1u));
         return acc;
       }
       uint32_t acc = 0;
@@ -414,44 +417,71 @@ struct GenSource {
     }
   }
 
-  // one GBM step to slot q (all assets); optionally record words/normals
-  __device__ __forceinline__ void step(int q, uint32_t* wout, T* zout, uint32_t npath) {
-    T z[A];
+  // What one GBM step needs from memory: its words and its time step.
+  // Fetched one slot ahead in the generation loop, so that the scalar and
+  // LDS load latency overlaps the previous slot's arithmetic.
+  struct Pre {
     uint32_t xw[A];
-    words(q, xw);
+    T dt, sdt;
+  };
+  __device__ __forceinline__ void fetch(int q, Pre& p) {
+    words(q, p.xw);
+    p.dt = slotc[2 * q];
+    p.sdt = slotc[2 * q + 1];
+  }
+  // the normals and the log-Euler step of one slot
+  __device__ __forceinline__ void advance(const Pre& p, T (&z)[A]) {
 #pragma unroll
-    for (int a = 0; a < A; ++a) {
-      const uint32_t w = (uint32_t)(q * A + a);
-      const uint32_t x32 = xw[a];
-      z[a] = Num<T>::normal_word(x32);
-      if (wout) wout[(size_t)w * npath + path] = x32;
-      if (zout) zout[(size_t)w * npath + path] = z[a];
-    }
-    const T dt = slotc[2 * q], sdt = slotc[2 * q + 1];
+    for (int a = 0; a < A; ++a) z[a] = Num<T>::normal_word(p.xw[a]);
 #pragma unroll
     for (int a = 0; a < A; ++a) {
       T wa = T(0);
 #pragma unroll
       for (int k = 0; k <= a; ++k) wa += M.L[a][k] * z[k];
-      x[a] = x[a] + M.mu[a] * dt + (M.sig[a] * sdt) * wa;
+      x[a] = x[a] + M.mu[a] * p.dt + (M.sig[a] * p.sdt) * wa;
     }
   }
 
+  // one GBM step to slot q (all assets); optionally record words/normals
+  __device__ __forceinline__ void step(int q, uint32_t* wout, T* zout, uint32_t npath) {
+    Pre p;
+    fetch(q, p);
+    T z[A];
+    advance(p, z);
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      const size_t w = (size_t)(q * A + a);
+      if (wout) wout[w * npath + path] = p.xw[a];
+      if (zout) zout[w * npath + path] = z[a];
+    }
+  }
+
+  // Generates slots up to s + WS - 1 (from the spot again on a backward
+  // read) and keeps slots s .. s+WS-1 in the window.
   __device__ __forceinline__ void refill(T (&win)[kWindow], int s) {
-    if (s < next_slot) {            // backward read: regenerate from the spot
+    if (s < next_slot) {
 #pragma unroll
       for (int a = 0; a < A; ++a) x[a] = T(0);
       next_slot = 0;
     }
-    while (next_slot < s) { step(next_slot, nullptr, nullptr, 0); ++next_slot; }
-    const int cnt = min(WS, n_slots - s);
+    const int end = s + min(WS, n_slots - s);
+    Pre cur;
+    fetch(next_slot, cur);
 #pragma unroll 1
-    for (int j = 0; j < cnt; ++j) {
-      step(s + j, nullptr, nullptr, 0);
+    for (int q = next_slot; q < end; ++q) {
+      Pre nx;
+      const bool more = q + 1 < end;
+      if (more) fetch(q + 1, nx);
+      T z[A];
+      advance(cur, z);
+      if (q >= s) {
+        const int j = q - s;
 #pragma unroll
-      for (int a = 0; a < A; ++a) win[(j * A + a) & (kWindow - 1)] = M.s0[a] * Num<T>::expv(x[a]);
+        for (int a = 0; a < A; ++a) win[(j * A + a) & (kWindow - 1)] = M.s0[a] * Num<T>::expv(x[a]);
+      }
+      if (more) cur = nx;
     }
-    next_slot = s + cnt;
+    next_slot = end;
     base = s;
   }
 
@@ -754,13 +784,19 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
     __shared__ __align__(16) T win_lds[kLdsWin * 256 * P];   // [entry][thread][P], blockDim <= 256
     mem_win = (lwptr<T>)win_lds;
   }
-  int item = blockIdx.x;
+  // Work items come from the atomic queue (persistent batches) or in a
+  // fixed grid stride (single instrument: the grid is at most what fits on
+  // the chip, so per-block set-up is paid once per resident block).
+  double bs = 0.0, bss = 0.0;   // fixed stride: this thread's sums over its tiles
+  int item = (int)blockIdx.x - (int)gridDim.x;
   for (;;) {
     if (g.queue) {
       if (threadIdx.x == 0) item_s = (int)atomicAdd(g.queue, 1u);
       __syncthreads();
       item = item_s;
       __syncthreads();
+    } else {
+      item += (int)gridDim.x;
     }
     if (item >= g.n_work) break;
     // item -> (instance, tile): consecutive items cover one instance's tiles
@@ -796,18 +832,25 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
         }
       }
     }
+    if (!g.queue) {          // one instrument: per-thread sums over its tiles, reduced once below
+      bs += s; bss += ss;
+      continue;
+    }
     block_sum2(s, ss, red);
-    // Publish the tile's partial; the block that completes an instance's
-    // last tile sums all its partials in tile order (deterministic whichever
-    // block is last) and writes the instance's result.
+    // Queue: publish the tile's partial; the block that completes an
+    // instance's last tile sums all its partials in tile order
+    // (deterministic whichever block is last) and writes the result.
+    // (release by every block: a write-back of this XCD's L2; acquire, an
+    // L2 invalidation, only by the last one)
     if (threadIdx.x == 0) {
       g.partial[D.first_item + wi.y] = make_double2(s, ss);
-      __threadfence();
-      last_s = atomicAdd(&g.done[wi.x], 1u) == D.n_tiles - 1u;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      last_s = __hip_atomic_fetch_add(&g.done[wi.x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+               D.n_tiles - 1u;
     }
     __syncthreads();
     if (last_s) {
-      __threadfence();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       double a = 0.0, b = 0.0;
       for (uint32_t i = threadIdx.x; i < D.n_tiles; i += blockDim.x) {
         const double2 q = g.partial[D.first_item + i];
@@ -816,10 +859,37 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
       block_sum2(a, b, red);
       if (threadIdx.x == 0) {
         g.result[wi.x] = make_double2(a, b);
-        __threadfence_system();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: host-mapped memory
       }
     }
-    if (!g.queue) break;
+  }
+  if (!g.queue) {
+    // One block reduction, one partial and one counter increment per block
+    // (a returning atomic is a long round trip, paid once per block rather
+    // than per tile); the last block sums the per-block partials in block
+    // order.  Each thread's tiles are fixed by the stride, so the result is
+    // deterministic.
+    block_sum2(bs, bss, red);
+    if (threadIdx.x == 0) {
+      g.partial[blockIdx.x] = make_double2(bs, bss);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      last_s = __hip_atomic_fetch_add(&g.done[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+               gridDim.x - 1u;
+    }
+    __syncthreads();
+    if (last_s) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      double a = 0.0, b = 0.0;
+      for (uint32_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
+        const double2 q = g.partial[i];
+        a += q.x; b += q.y;
+      }
+      block_sum2(a, b, red);
+      if (threadIdx.x == 0) {
+        g.result[0] = make_double2(a, b);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: host-mapped memory
+      }
+    }
   }
 }
 

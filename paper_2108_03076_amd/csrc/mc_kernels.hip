@@ -70,7 +70,7 @@ __global__ void k_prep(const double* a, double* l, int* status, uint32_t* zero, 
     }
   }
   status[i] = ok ? 0 : 1;
-  __threadfence_system();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: host-mapped memory
 }
 
 __global__ void k_sobol_hi(const uint32_t* v, uint32_t* hi, int n_rows, int dims, int bits) {
