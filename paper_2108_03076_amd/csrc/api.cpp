@@ -577,14 +577,22 @@ int finish(pmc_ctx* c, int n_inst, const std::vector<uint64_t>& n_paths, const s
 }
 
 // Launches the Monte Carlo kernel with the requested payoff engine.
+// Simulated asset-dates per path up to which a single-instrument launch
+// counts as short.
+constexpr int64_t kShortItem = 64;
+
 // lanes: paths per lane (compiled engine with stored paths only).  Without a
-// work queue the kernel strides over the items, and the grid is capped at
-// the blocks that fit on the chip at once.
+// work queue the kernel strides over the items.  Short items (few simulated
+// asset-dates per path) run on a grid capped at the blocks that fit on the
+// chip at once, so per-block set-up and the block's completion atomic are
+// paid once per resident block; long items keep one block per item, whose
+// dispatch balances the load better than a fixed stride.
 int launch_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec, bool mem, const McLaunch& L,
-                  int grid, int block, int lanes = 1) {
+                  int grid, int block, int lanes = 1, int64_t asset_dates = 0) {
   const int A = (int)p->prog.assets.size();
+  const bool cap = !L.queue && asset_dates <= kShortItem;
   if (o->engine == PMC_ENGINE_INTERPRETER) {
-    if (!L.queue) {
+    if (cap) {
       const std::string key = "interp/" + std::to_string(prec) + "/" + std::to_string(o->rng) + "/" +
                               std::to_string(A) + "/" + std::to_string(p->prog.n_regs <= 7 ? 8 : 32) + "/" +
                               std::to_string(block);
@@ -599,7 +607,7 @@ int launch_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec, 
   std::string err;
   int st = p->jit.get(p->prog, c->device, prec, o->rng, A, mem, &f, err, lanes);
   if (st != PMC_OK) return fail(c, st, err);
-  if (!L.queue) {
+  if (cap) {
     char kb[64];
     std::snprintf(kb, sizeof kb, "jit/%p/%d", (const void*)f, block);
     const std::string key = kb;
@@ -683,10 +691,10 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
     }
     if (n_slots == 0) L.paths = nullptr;
     HIP_TRY(c, hipEventRecord(c->evk[1], c->stream));
-    st = launch_engine(c, p, o, prec, n_slots > 0, L, (int)tiles, block, lanes);
+    st = launch_engine(c, p, o, prec, n_slots > 0, L, (int)tiles, block, lanes, (int64_t)n_slots * A);
   } else {
     HIP_TRY(c, hipEventRecord(c->evk[1], c->stream));
-    st = launch_engine(c, p, o, prec, false, L, (int)tiles, block);
+    st = launch_engine(c, p, o, prec, false, L, (int)tiles, block, 1, (int64_t)n_slots * A);
   }
   if (st != PMC_OK) return st;
   HIP_TRY(c, hipEventRecord(c->evk[2], c->stream));

@@ -404,8 +404,8 @@ struct GenSource {
     }
   }
 
-  // the A words of slot q (words q*A .. q*A+A-1); the table case issues its
-  // A loads together
+  // the A words of slot q (words q*A .. q*A+A-1); with the Sobol LDS table
+  // the A loads are issued together
   __device__ __forceinline__ void words(int q, uint32_t (&xw)[A]) {
     const uint32_t w0 = (uint32_t)(q * A);
     if (RNG == 1 && use_lo) {
@@ -417,42 +417,25 @@ struct GenSource {
     }
   }
 
-  // What one GBM step needs from memory: its words and its time step.
-  // Fetched one slot ahead in the generation loop, so that the scalar and
-  // LDS load latency overlaps the previous slot's arithmetic.
-  struct Pre {
+  // one GBM step to slot q (all assets); optionally record words/normals
+  __device__ __forceinline__ void step(int q, uint32_t* wout, T* zout, uint32_t npath) {
     uint32_t xw[A];
-    T dt, sdt;
-  };
-  __device__ __forceinline__ void fetch(int q, Pre& p) {
-    words(q, p.xw);
-    p.dt = slotc[2 * q];
-    p.sdt = slotc[2 * q + 1];
-  }
-  // the normals and the log-Euler step of one slot
-  __device__ __forceinline__ void advance(const Pre& p, T (&z)[A]) {
+    words(q, xw);
+    T z[A];
 #pragma unroll
-    for (int a = 0; a < A; ++a) z[a] = Num<T>::normal_word(p.xw[a]);
+    for (int a = 0; a < A; ++a) {
+      z[a] = Num<T>::normal_word(xw[a]);
+      const size_t w = (size_t)(q * A + a);
+      if (wout) wout[w * npath + path] = xw[a];
+      if (zout) zout[w * npath + path] = z[a];
+    }
+    const T dt = slotc[2 * q], sdt = slotc[2 * q + 1];
 #pragma unroll
     for (int a = 0; a < A; ++a) {
       T wa = T(0);
 #pragma unroll
       for (int k = 0; k <= a; ++k) wa += M.L[a][k] * z[k];
-      x[a] = x[a] + M.mu[a] * p.dt + (M.sig[a] * p.sdt) * wa;
-    }
-  }
-
-  // one GBM step to slot q (all assets); optionally record words/normals
-  __device__ __forceinline__ void step(int q, uint32_t* wout, T* zout, uint32_t npath) {
-    Pre p;
-    fetch(q, p);
-    T z[A];
-    advance(p, z);
-#pragma unroll
-    for (int a = 0; a < A; ++a) {
-      const size_t w = (size_t)(q * A + a);
-      if (wout) wout[w * npath + path] = p.xw[a];
-      if (zout) zout[w * npath + path] = z[a];
+      x[a] = x[a] + M.mu[a] * dt + (M.sig[a] * sdt) * wa;
     }
   }
 
@@ -464,24 +447,15 @@ struct GenSource {
       for (int a = 0; a < A; ++a) x[a] = T(0);
       next_slot = 0;
     }
-    const int end = s + min(WS, n_slots - s);
-    Pre cur;
-    fetch(next_slot, cur);
+    while (next_slot < s) { step(next_slot, nullptr, nullptr, 0); ++next_slot; }
+    const int cnt = min(WS, n_slots - s);
 #pragma unroll 1
-    for (int q = next_slot; q < end; ++q) {
-      Pre nx;
-      const bool more = q + 1 < end;
-      if (more) fetch(q + 1, nx);
-      T z[A];
-      advance(cur, z);
-      if (q >= s) {
-        const int j = q - s;
+    for (int j = 0; j < cnt; ++j) {
+      step(s + j, nullptr, nullptr, 0);
 #pragma unroll
-        for (int a = 0; a < A; ++a) win[(j * A + a) & (kWindow - 1)] = M.s0[a] * Num<T>::expv(x[a]);
-      }
-      if (more) cur = nx;
+      for (int a = 0; a < A; ++a) win[(j * A + a) & (kWindow - 1)] = M.s0[a] * Num<T>::expv(x[a]);
     }
-    next_slot = end;
+    next_slot = s + cnt;
     base = s;
   }
 
