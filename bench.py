@@ -48,7 +48,8 @@ OPS_PHILOX = 15          # 10 rounds x (2 mul-hi, 2 mul-lo, 2 xor3) / 4 words
 # counters read for a 256 MiB device-to-device copy in the same run (FETCH
 # reads 0.5 KiB per KiB copied, WRITE 1.0).  Valid only for the engine sources
 # it was measured on (hash below); otherwise reported as null.
-TRAFFIC = {"engine_sha256": None, "fetch_kib": None, "write_kib": None, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC = {"engine_sha256": "789863e1275b0887557c21e9924a7a994503346243b482436aef18e36b58a6b5",
+           "fetch_kib": 1569.5, "write_kib": 96.03, "fetch_scale": 2.0, "write_scale": 1.0}
 ENGINE_SOURCES = ("paper_2108_03076_amd/csrc/mc_engine.h", "paper_2108_03076_amd/csrc/pmc_device.h",
                   "paper_2108_03076_amd/csrc/codegen.cpp")
 
