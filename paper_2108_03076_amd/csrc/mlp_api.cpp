@@ -261,6 +261,18 @@ extern "C" int pmc_mlp_set_params(pmc_mlp* m, const float* in) {
 extern "C" int pmc_mlp_infer(pmc_mlp* m, const float* x, float* y, int64_t n) {
   if (!m || !x || !y || n < 1 || n > (1ll << 30)) return PMC_E_ARG;
   hipStream_t s = ctx_stream(m->ctx);
+  if (m->width == 256) {   // one fused kernel: all four layers per block of 128 samples
+    const float* w = m->master.as<float>();
+    const int chunk = 1 << 24;
+    for (int64_t o = 0; o < n; o += chunk) {
+      const int k = (int)std::min<int64_t>(chunk, n - o);
+      MLP_TRY(m, mlp_infer256(x + o * m->n_in, k, m->n_in, m->lohi.as<float>(), m->W[0].as<__bf16>(), w + m->ob[0],
+                              m->W[1].as<__bf16>(), w + m->ob[1], m->W[2].as<__bf16>(), w + m->ob[2],
+                              m->W[3].as<__bf16>(), w + m->ob[3], (float)m->y_scale, y + o, s));
+    }
+    MLP_TRY(m, hipStreamSynchronize(s));
+    return PMC_OK;
+  }
   const int chunk = 1 << 16;
   for (int64_t o = 0; o < n; o += chunk) {
     const int k = (int)std::min<int64_t>(chunk, n - o);

@@ -31,5 +31,12 @@ hipError_t mlp_adam(float* w, float* m, float* v, const float* g, int n, float l
                     float c1, float c2, hipStream_t s);
 hipError_t mlp_pack(const float* master, int out, int in, int out_pad, int in_pad, __bf16* W, __bf16* Wt,
                     hipStream_t s);
+// Fused inference of the width-256 network for n samples: y[i] = price of
+// row i of x [n][n_in] (lohi: the input box, lo[0..31] then hi[0..31]; W1
+// [256][16], W2 and W3 [256][256], W4 [32][256] padded BF16 weights; b*
+// FP32 biases).
+hipError_t mlp_infer256(const float* x, int n, int n_in, const float* lohi, const __bf16* W1, const float* b1,
+                        const __bf16* W2, const float* b2, const __bf16* W3, const float* b3, const __bf16* W4,
+                        const float* b4, float y_scale, float* y, hipStream_t s);
 
 }  // namespace pmc

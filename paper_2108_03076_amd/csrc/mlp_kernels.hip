@@ -15,10 +15,29 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 __device__ __forceinline__ float from_bf16(__bf16 x) { return (float)x; }
 
-// GELU with the exact (erf) form and its derivative.
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf by Abramowitz & Stegun 7.1.26 (Hastings' rational form):
+// erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-x^2},
+// t = 1 / (1 + p x), x >= 0, |error| <= 1.5e-7 (far below the BF16 rounding
+// of the activations it feeds); odd symmetry for x < 0.
+__device__ __forceinline__ float erf_as(float v) {
+  const float x = fabsf(v);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+  float q = fmaf(1.061405429f, t, -1.453152027f);
+  q = fmaf(q, t, 1.421413741f);
+  q = fmaf(q, t, -0.284496736f);
+  q = fmaf(q, t, 0.254829592f);
+  const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * x * x);
+  return copysignf(fmaf(-q * t, e, 1.0f), v);
+}
+// GELU with the erf form and its derivative (the same erf in training and
+// inference).
+__device__ __forceinline__ float gelu(float z) {
+  const float h = 0.5f * z;
+  return fmaf(h, erf_as(z * 0.70710678118654752f), h);
+}
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+  return fmaf(0.5f, erf_as(z * 0.70710678118654752f), 0.5f) +
+         z * 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z);
 }
 
 // C = A * Bt^T with A [M x K] and Bt [N x K] row-major BF16 (K contiguous).
@@ -216,6 +235,99 @@ __global__ void k_pack(const float* __restrict__ master, int out, int in, int ou
   Wt[(size_t)k * out_pad + o] = b;
 }
 
+// Fused inference for width 256: a block carries 128 samples through the
+// four layers.  Wave w owns rows 32w .. 32w+31 of the block's activations,
+// kept in LDS as BF16 between layers (rows padded by 8 elements, so the 16
+// rows of a half-wave's A-fragment reads fall on distinct banks), and
+// computes all 256 columns of its rows: eight 32 x 32 MFMA tiles share each
+// A fragment, the weights stream from L2.  The k order, the MFMA instruction
+// and the epilogues are those of the per-layer kernels, so the outputs are
+// the same bit for bit.
+constexpr int kInferRows = 128;
+constexpr int kInferW = 256;
+constexpr int kInferLd = kInferW + 8;
+
+template <int K>
+__device__ __forceinline__ void infer_layer(const __bf16* my, const __bf16* __restrict__ Wl, int ntiles,
+                                            f32x16 (&acc)[8]) {
+  const int lane = threadIdx.x & 63, r = lane & 31, kh = (lane >> 5) * 8;
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
+#pragma unroll 4
+  for (int k = 0; k < K; k += 16) {
+    const bf16x8 a = *reinterpret_cast<const bf16x8*>(my + r * kInferLd + k + kh);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (t < ntiles) {
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(Wl + (size_t)(32 * t + r) * K + k + kh);
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void infer_hidden_epilogue(__bf16* my, const float* __restrict__ bias,
+                                                      const f32x16 (&acc)[8]) {
+  const int lane = threadIdx.x & 63, r = lane & 31;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int col = 32 * t + r;
+    const float b = bias[col];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int row = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      my[row * kInferLd + col] = to_bf16(gelu(acc[t][e] + b));
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mlp_infer256(const float* __restrict__ x, int n, int n_in,
+                                                      const float* __restrict__ lohi, const __bf16* __restrict__ W1,
+                                                      const float* __restrict__ b1, const __bf16* __restrict__ W2,
+                                                      const float* __restrict__ b2, const __bf16* __restrict__ W3,
+                                                      const float* __restrict__ b3, const __bf16* __restrict__ W4,
+                                                      const float* __restrict__ b4, float y_scale,
+                                                      float* __restrict__ y) {
+  __shared__ __bf16 act[kInferRows * kInferLd];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t g0 = (int64_t)blockIdx.x * kInferRows + 32 * w;   // global row of the wave's first row
+  __bf16* my = act + 32 * w * kInferLd;
+  {   // scaled inputs in columns 0..15 (zero beyond n_in and beyond n)
+    const int row = lane & 31, j0 = (lane >> 5) * 8;
+    const int64_t gi = g0 + row;
+#pragma unroll
+    for (int j = j0; j < j0 + 8; ++j) {
+      float v = 0.0f;
+      if (gi < n && j < n_in) v = 2.0f * (x[gi * n_in + j] - lohi[j]) / (lohi[32 + j] - lohi[j]) - 1.0f;
+      my[row * kInferLd + j] = to_bf16(v);
+    }
+  }
+  __syncthreads();
+  f32x16 acc[8];
+  infer_layer<16>(my, W1, 8, acc);
+  __syncthreads();
+  infer_hidden_epilogue(my, b1, acc);
+  __syncthreads();
+  infer_layer<kInferW>(my, W2, 8, acc);
+  __syncthreads();
+  infer_hidden_epilogue(my, b2, acc);
+  __syncthreads();
+  infer_layer<kInferW>(my, W3, 8, acc);
+  __syncthreads();
+  infer_hidden_epilogue(my, b3, acc);
+  __syncthreads();
+  infer_layer<kInferW>(my, W4, 1, acc);   // output layer: rows of W4 padded to 32, column 0 real
+  if ((lane & 31) == 0) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int row = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      if (g0 + row < n) y[g0 + row] = (acc[0][e] + b4[0]) * y_scale;
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t mlp_gemm_f32(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb, int splits,
@@ -264,6 +376,14 @@ hipError_t mlp_rowsum(const __bf16* dZt, int B, int rows, float* g, hipStream_t 
 hipError_t mlp_adam(float* w, float* m, float* v, const float* g, int n, float lr, float b1, float b2, float eps,
                     float c1, float c2, hipStream_t s) {
   hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+hipError_t mlp_infer256(const float* x, int n, int n_in, const float* lohi, const __bf16* W1, const float* b1,
+                        const __bf16* W2, const float* b2, const __bf16* W3, const float* b3, const __bf16* W4,
+                        const float* b4, float y_scale, float* y, hipStream_t s) {
+  if (n < 1 || n_in < 1 || n_in > 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mlp_infer256, dim3((n + kInferRows - 1) / kInferRows), dim3(256), 0, s, x, n, n_in, lohi, W1,
+                     b1, W2, b2, W3, b3, W4, b4, y_scale, y);
   return hipGetLastError();
 }
 hipError_t mlp_pack(const float* master, int out, int in, int out_pad, int in_pad, __bf16* W, __bf16* Wt,

@@ -98,6 +98,37 @@ def test_payoffs_on_stored_paths(name):
     assert r["sum"] == pytest.approx(gpu.sum(), rel=1e-12, abs=1e-9)
 
 
+@pytest.mark.parametrize("name", ["c3_short", "c2", "c1"])
+@pytest.mark.parametrize("n,offset", [(1028, 0), (1001, 0), (4, 0), (1000, 1)])
+def test_stored_paths_lane_layouts(name, n, offset):
+    """The compiled evaluator of stored paths takes 4 (FP32) or 2 (FP64)
+    paths per lane when the path count and the buffer alignment allow it and
+    one otherwise (a count not a multiple of 4, a buffer one element off);
+    every layout gives the interpreter's per-path payoffs exactly."""
+    import paper_2108_03076_amd as P
+    cfg = CASES[name]
+    print(f"[parity] lanes {name} n={n} offset={offset}", flush=True)
+    pay, days, S, _, _, paths = _gen(cfg, n)
+    if offset:
+        big = torch.empty(paths.numel() + offset, dtype=paths.dtype, device="cuda")
+        big[offset:].copy_(paths)
+        paths = big[offset:]
+    dt = torch.float64 if cfg.precision == "f64" else torch.float32
+    outs = {}
+    for engine in ("interpreter", "compiled"):
+        out = torch.empty(n, dtype=dt, device="cuda")
+        r = P.eval_paths(pay, paths, cfg.tenv, cfg.params, **model_kw(cfg),
+                         **opts_kw(cfg, n, payoffs=out, engine=engine))
+        outs[engine] = (out.cpu(), r)
+    assert torch.equal(outs["interpreter"][0], outs["compiled"][0])
+    ref = oracle_problem(cfg).payoffs_on_paths(S)
+    gpu = outs["compiled"][0].double().numpy()
+    tol = 1e-12 if cfg.precision == "f64" else 1e-5
+    band = tie_band(oracle_problem(cfg), S, 3e-5) if cfg.precision == "f32" else np.zeros(n, bool)
+    assert not ((np.abs(gpu - ref) > tol * np.maximum(np.abs(ref), 1.0)) & ~band).any()
+    assert outs["compiled"][1]["sum"] == pytest.approx(gpu.sum(), rel=1e-12, abs=1e-9)
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("mode", ["fused", "two_phase"])
 @pytest.mark.parametrize("engine", ["interpreter", "compiled"])

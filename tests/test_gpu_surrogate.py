@@ -46,6 +46,23 @@ def test_forward_matches_reference():
     assert np.corrcoef(gpu, ref)[0, 1] > 0.999
 
 
+def test_fused_inference_matches_layer_forward():
+    """The fused inference kernel (all layers per block of 128 samples)
+    computes what the per-layer training forward computes: that forward's
+    loss at the fused predictions is zero up to the output scaling's
+    rounding; rows are independent of the batch they are in."""
+    sur = _net(seed=7)
+    x, _ = _data(1000, 9)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    yf = torch.empty(1000, dtype=torch.float32, device="cuda")
+    sur.infer(xt, yf)
+    loss, _ = sur.loss_grad(xt, yf)
+    assert loss < 1e-12, loss
+    part = torch.empty(300, dtype=torch.float32, device="cuda")
+    sur.infer(xt[:300].contiguous(), part)
+    assert torch.equal(part, yf[:300])
+
+
 def test_loss_and_gradients_match_reference():
     sur = _net(seed=3)
     p = sur.get_params().astype(np.float64)
