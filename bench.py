@@ -108,6 +108,42 @@ def cpu_baseline(cfg, n_paths):
     return n_paths * len(prob.days) / dt, dt
 
 
+def _oracle_chunk(args):
+    cfg_name, lo, hi = args
+    import warnings
+    warnings.filterwarnings("ignore", message="The balance properties")   # partial Sobol ranges
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import workloads as W
+    from oracle import mc
+    cfg = W.CONFIGS[cfg_name]
+    prob = mc.Problem(cfg.il, asset_labels=cfg.asset_labels, param_labels=cfg.param_labels,
+                      params=cfg.params, tenv=cfg.tenv_dict(), spot=cfg.spot, vol=cfg.vol, corr=cfg.corr,
+                      rate=cfg.rate, years_per_day=cfg.years_per_day, rng=cfg.rng, seed=cfg.seed,
+                      precision=cfg.precision)
+    with threadpool_limits(limits=1):
+        pay = prob.payoffs(np.arange(lo, hi))
+    return float(pay.sum()), len(prob.days)
+
+
+def cpu_baseline_all_cores(cfg, n_paths):
+    """The oracle over all host cores: contiguous path ranges in separate
+    processes (exact, since the streams are counter based and indexable)."""
+    import multiprocessing as mp
+    n = min(os.cpu_count() or 1, 16)
+    bounds = [(cfg_key(cfg), i * n_paths // n, (i + 1) * n_paths // n) for i in range(n)]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(n) as pool:
+        res = pool.map(_oracle_chunk, bounds)
+    dt = time.perf_counter() - t0
+    return n_paths * res[0][1] / dt, dt, n
+
+
+def cfg_key(cfg):
+    import workloads as W
+    return next(k for k, v in W.CONFIGS.items() if v is cfg)
+
+
 def surrogate_workload(ctx, args):
     """Labels from the batched Monte Carlo engine (2^16 Philox paths per
     point), training on the GPU, the Monte Carlo judge (2^22 paths, another
@@ -203,11 +239,20 @@ def main():
                                    "(multi-GPU sharding is described in the design notes, not built)"}))
         sys.exit(2)
 
+    # The oracle's CPU timings run first, before this process touches the
+    # GPU (the all-cores run starts worker processes).
+    import workloads as W
+    cpu = None
+    if not args.quick and not args.no_cpu_baseline:
+        n_cpu = 1 << 20
+        v, dt = cpu_baseline(W.C2, n_cpu)
+        va, dta, ncores = cpu_baseline_all_cores(W.C2, n_cpu)
+        cpu = (n_cpu, v, dt, va, dta, ncores)
+
     import numpy as np
     import torch
 
     import paper_2108_03076_amd as P
-    import workloads as W
 
     ctx = P.Context(0)
     if args.copy_calibration:
@@ -275,6 +320,27 @@ def main():
         extra["C1_fp64_european"] = {"ms_per_step": s1 * 1e3, "path_dates_per_s": c1.n_paths / s1,
                                      "kernel_ms": float(np.mean([o["eval_ms"] for o in o1])),
                                      "price": o1[-1]["price"], "std_err": o1[-1]["std_err"]}
+    if want("C1"):
+        # C1 swept over the path count (2^23 is the paper's vanilla size):
+        # launch-latency bound at 2^16, FP64-arithmetic bound at the top
+        from oracle.closed_form import bs_call
+        ref = bs_call(100.0, 100.0, c1.rate, 0.2, 1.0)
+        sweep = {}
+        for lg in (16, 18, 20, 23, 26):
+            kwn = dict(kw1, n_paths=1 << lg)
+            sn, on = time_steps(lambda: P.price(pay1, c1.tenv, c1.params, **kwn), 5, 1)
+            sweep[f"2^{lg}"] = {"ms_per_step": sn * 1e3, "path_dates_per_s": (1 << lg) / sn,
+                                "kernel_ms": float(np.mean([o["eval_ms"] for o in on])),
+                                "error_vs_black_scholes_in_se": (on[-1]["price"] - ref) / on[-1]["std_err"]}
+        extra["C1_fp64_european_sweep"] = sweep
+    if want("C2D"):
+        # the double option: two calls on a correlated two-asset model
+        c2d = W.C2D
+        pay2d, kw2d = setup(c2d)
+        sd, od = time_steps(lambda: P.price(pay2d, c2d.tenv, c2d.params, **kw2d), args.steps, args.warmup)
+        extra["C2D_double_call"] = {"ms_per_step": sd * 1e3, "path_dates_per_s": c2d.n_paths / sd,
+                                    "kernel_ms": float(np.mean([o["eval_ms"] for o in od])),
+                                    "price": od[-1]["price"], "std_err": od[-1]["std_err"]}
     if want("C2i"):
         # the headline workload with the bytecode interpreter instead of the
         # compiled payoff
@@ -332,9 +398,10 @@ def main():
         extra["C5_surrogate"] = surrogate_workload(ctx, args)
     line["workloads"] = extra
 
-    if not args.quick and not args.no_cpu_baseline:
-        n_cpu = 1 << 20
-        v, dt = cpu_baseline(c2, n_cpu)
+    if cpu is not None:
+        n_cpu, v, dt, va, dta, ncores = cpu
+        line["cpu_oracle_all_cores"] = {"value": va, "unit": "path-dates/s", "cores": ncores,
+                                        "seconds": dta, "paths": n_cpu}
         line["cpu_baseline"] = {"value": v, "unit": "path-dates/s", "cores": 1, "kind": "oracle",
                                 "sample": f"first {n_cpu} of the 2^20 Sobol paths of the headline workload "
                                           f"({dt:.1f} s, FP64 numpy, one thread)",

@@ -51,6 +51,7 @@ CASES = {
     "c2": W.C2,
     "c1": W.C1,
     "c2_philox": _small(W.C2, rng="philox"),
+    "c2d": W.C2D,
 }
 
 

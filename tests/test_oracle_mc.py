@@ -177,3 +177,26 @@ def test_sobol_and_philox_streams_agree_statistically():
     ma, sa = mc.estimate(pa)
     mb, sb = mc.estimate(pb)
     assert abs(ma - mb) < 3 * math.hypot(sa, sb)
+
+
+def test_double_call_is_sum_of_its_legs_and_black_scholes():
+    """The double option is linear in its legs: on every path its payoff is
+    the sum of the two calls' payoffs on the same correlated paths, and the
+    price agrees with the sum of the two Black-Scholes prices within 4
+    standard errors."""
+    import math
+    from oracle import closed_form as cf
+    cfg = W.C2D
+    n = 4096
+    kw = dict(asset_labels=cfg.asset_labels, param_labels=cfg.param_labels, params=cfg.params,
+              tenv=cfg.tenv_dict(), spot=cfg.spot, vol=cfg.vol, corr=cfg.corr, rate=cfg.rate,
+              years_per_day=cfg.years_per_day, rng=cfg.rng, seed=cfg.seed, precision="f64")
+    both = mc.Problem(cfg.il, **kw).payoffs(np.arange(n))
+    leg = lambda a: (f"(if (lt (model K{a} 0) (model S{a} (tvar T))) "
+                     f"(mult (sub (model S{a} (tvar T)) (model K{a} 0)) (payoff (tvar T) X Y)) (real 0.0))")
+    legs = sum(mc.Problem(leg(a), **kw).payoffs(np.arange(n)) for a in (1, 2))
+    assert np.allclose(both, legs, rtol=1e-15, atol=1e-12)
+    p, se = mc.estimate(both)
+    T = 252 / 252.0
+    ref = cf.bs_call(100.0, 100.0, 0.03, 0.2, T) + cf.bs_call(100.0, 95.0, 0.03, 0.3, T)
+    assert abs(p - ref) < 4 * se, (p, ref, se)

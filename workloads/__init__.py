@@ -63,6 +63,18 @@ BASKET_CALL = """
 """
 
 
+# Double option (the paper's third benchmark contract, Table 1): two
+# European calls on a two-asset model, both paying at day T.
+DOUBLE_CALL = """
+(add (if (lt (model K1 0) (model S1 (tvar T)))
+         (mult (sub (model S1 (tvar T)) (model K1 0)) (payoff (tvar T) X Y))
+         (real 0.0))
+     (if (lt (model K2 0) (model S2 (tvar T)))
+         (mult (sub (model S2 (tvar T)) (model K2 0)) (payoff (tvar T) X Y))
+         (real 0.0)))
+"""
+
+
 def _worst(day):
     """min over the three assets on a day offset (an ILTExprZ)."""
     return f"(min (min (model S1 {day}) (model S2 {day})) (model S3 {day}))"
@@ -145,6 +157,13 @@ C3 = Config(
     years_per_day=1.0 / 252.0, n_paths=1 << 20, rng="philox", seed=42, precision="f32")
 
 
+C2D = Config(
+    name="double call, 2 assets (rho 0.5), 1 date, philox",
+    il=DOUBLE_CALL, asset_labels=["S1", "S2"], param_labels=["K1", "K2"], params=[100.0, 95.0],
+    tvars=["T"], tenv=[252], spot=[100.0, 100.0], vol=[0.2, 0.3], corr=corr_equi(2, 0.5), rate=0.03,
+    years_per_day=1.0 / 252.0, n_paths=1 << 20, rng="philox", seed=42, precision="f32")
+
+
 def c4_instances(n_inst=1024, seed=42):
     """Per-instance template values and parameters for the batched workload:
     T days uniform in {252..1260}, K uniform in [80, 120], barrier b*100 with
@@ -186,7 +205,7 @@ C5 = Config(
     seed=42, precision="f32", notes={"train_points": 1 << 20, "test_points": 4096,
                                      "judge_paths": 1 << 22, "infer_batch": 65536})
 
-CONFIGS = {"C1": C1, "C2": C2, "C3": C3, "C4": C4, "C5": C5}
+CONFIGS = {"C1": C1, "C2": C2, "C2D": C2D, "C3": C3, "C4": C4, "C5": C5}
 
 
 # Risk workload: bump-and-revalue Greeks (delta, gamma per spot; vega per
