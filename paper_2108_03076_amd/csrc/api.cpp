@@ -675,12 +675,16 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   L.partial = (double2*)c->partial.p;
   L.n_work = (int)tiles;
   L.payoff_out = o->payoffs_dev;
+  // Timing markers: ev0 (start), evk[0] (generation start, two-phase
+  // only), evk[1] (MC kernel start), ev1 (end); each is a queue entry, so
+  // only the ones a reported time needs are recorded.
   HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
   st = prep(c, L, 1, A);
   if (st != PMC_OK) return st;
   const int prec = sizeof(T) == 8 ? 1 : 0;
-  HIP_TRY(c, hipEventRecord(c->evk[0], c->stream));
-  if (mode == PMC_MODE_TWO_PHASE) {
+  const bool two_phase = mode == PMC_MODE_TWO_PHASE;
+  if (two_phase) {
+    HIP_TRY(c, hipEventRecord(c->evk[0], c->stream));
     if (given_paths) {
       L.paths = given_paths;
     } else {
@@ -697,13 +701,12 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
     st = launch_engine(c, p, o, prec, false, L, (int)tiles, block, 1, (int64_t)n_slots * A);
   }
   if (st != PMC_OK) return st;
-  HIP_TRY(c, hipEventRecord(c->evk[2], c->stream));
   HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
   HIP_TRY(c, hipEventSynchronize(c->ev1));
   float ms = 0, gen_ms = 0, eval_ms = 0;
   HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-  HIP_TRY(c, hipEventElapsedTime(&gen_ms, c->evk[0], c->evk[1]));
-  HIP_TRY(c, hipEventElapsedTime(&eval_ms, c->evk[1], c->evk[2]));
+  if (two_phase) HIP_TRY(c, hipEventElapsedTime(&gen_ms, c->evk[0], c->evk[1]));
+  HIP_TRY(c, hipEventElapsedTime(&eval_ms, c->evk[1], c->ev1));
   st = finish(c, 1, {N}, {n_slots}, mode, ms, out, gen_ms, eval_ms);
   if (st == PMC_OK) out->engine_used = engine_used(o);
   return st;
