@@ -121,10 +121,17 @@ int pmc_payoff_cut(pmc_ctx* ctx, const pmc_payoff* in, pmc_payoff** out);
 
 /* Device source of the compiled payoff engine for this payoff: the engine
  * kernel body plus the payoff expression translated to a HIP device function
- * (compile with -DPMC_REAL=float|double -DPMC_RNG=0|1 -DPMC_A=<assets>
- * -DPMC_MEM=0|1).  Copies at most cap bytes (NUL-terminated) to buf and
- * stores the full length (without NUL) in *len; buf may be NULL to query. */
-int pmc_payoff_source(const pmc_payoff* p, char* buf, size_t cap, size_t* len);
+ * (Sec. 6's code-generation route; compile with -DPMC_REAL=float|double
+ * -DPMC_RNG=0|1 -DPMC_A=<assets> -DPMC_MEM=0|1, optionally -DPMC_P=<paths
+ * per lane> -DPMC_FULL=<whole-path capacity> -DPMC_WAVES=<waves per SIMD>).
+ * tenv: NULL for the generic function (template values read per instance),
+ * else the function generated for that template environment, as the engine
+ * builds it for launches whose paths it holds whole (loopif iterations
+ * written out, fixed reads; the generic one if that would be too large).
+ * Copies at most cap bytes (NUL-terminated) to buf and stores the full
+ * length (without NUL) in *len; buf may be NULL to query.  Returns
+ * PMC_E_TENV for an invalid template environment. */
+int pmc_payoff_source(const pmc_payoff* p, const int32_t* tenv, char* buf, size_t cap, size_t* len);
 
 typedef struct pmc_payoff_info {
   int n_instr;      /* bytecode length */

@@ -103,7 +103,7 @@ _sig = {
     "pmc_payoff_load": (_i, [_vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_char_p), _i, C.POINTER(C.c_char_p), _i,
                              C.POINTER(C.c_char_p), _i, C.POINTER(_vp)]),
     "pmc_payoff_free": (None, [_vp]),
-    "pmc_payoff_source": (_i, [_vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "pmc_payoff_source": (_i, [_vp, C.POINTER(C.c_int32), C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "pmc_payoff_cut": (_i, [_vp, _vp, C.POINTER(_vp)]),
     "pmc_payoff_get_info": (_i, [_vp, C.POINTER(PayoffInfo)]),
     "pmc_payoff_grid": (_i, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _i, C.POINTER(_i), C.POINTER(_i)]),
@@ -246,12 +246,16 @@ class Payoff:
         new.assets, new.params, new.tvars = self.assets, self.params, self.tvars
         return new
 
-    def source(self):
-        """Device source of the compiled engine for this payoff."""
+    def source(self, tenv=None):
+        """Device source of the compiled engine for this payoff: generic, or
+        generated for one template environment (pmc_payoff_source)."""
+        tp = None
+        if tenv is not None:
+            t, tp = _i32(tenv if len(tenv) else [0])
         n = C.c_size_t()
-        self.ctx.check(lib.pmc_payoff_source(self.h, None, 0, C.byref(n)))
+        self.ctx.check(lib.pmc_payoff_source(self.h, tp, None, 0, C.byref(n)))
         buf = C.create_string_buffer(n.value + 1)
-        self.ctx.check(lib.pmc_payoff_source(self.h, buf, n.value + 1, C.byref(n)))
+        self.ctx.check(lib.pmc_payoff_source(self.h, tp, buf, n.value + 1, C.byref(n)))
         return buf.value.decode()
 
     def grid(self, tenv=()):

@@ -214,9 +214,17 @@ namespace {
 }  // namespace
 }  // namespace pmc
 
-extern "C" int pmc_payoff_source(const pmc_payoff* p, char* buf, size_t cap, size_t* len) {
+extern "C" int pmc_payoff_source(const pmc_payoff* p, const int32_t* tenv, char* buf, size_t cap, size_t* len) {
   if (!p || !len) return PMC_E_ARG;
-  const std::string s = std::string(pmc::kEngineSource) + "\n" + generate_payoff(p->prog);
+  pmc::Grid g;
+  const pmc::Grid* gp = nullptr;
+  if (tenv) {
+    std::string err;
+    const int st = pmc::plan(p->prog, tenv, g, err);
+    if (st != PMC_OK) return st;
+    if (pmc::unrolled_size(p->prog, g, p->prog.root, pmc::kMaxUnrolled + 1) <= pmc::kMaxUnrolled) gp = &g;
+  }
+  const std::string s = std::string(pmc::kEngineSource) + "\n" + generate_payoff(p->prog, gp);
   *len = s.size();
   if (buf && cap) {
     const size_t n = std::min(cap - 1, s.size());
@@ -588,7 +596,8 @@ constexpr int64_t kShortItem = 64;
 // paid once per resident block; long items keep one block per item, whose
 // dispatch balances the load better than a fixed stride.
 int launch_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec, bool mem, const McLaunch& L,
-                  int grid, int block, int lanes = 1, int64_t asset_dates = 0) {
+                  int grid, int block, int lanes = 1, int64_t asset_dates = 0, int full = 0,
+                  const int32_t* tenv = nullptr) {
   const int A = (int)p->prog.assets.size();
   const bool cap = !L.queue && asset_dates <= kShortItem;
   if (o->engine == PMC_ENGINE_INTERPRETER) {
@@ -605,7 +614,7 @@ int launch_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec, 
   }
   hipFunction_t f = nullptr;
   std::string err;
-  int st = p->jit.get(p->prog, c->device, prec, o->rng, A, mem, &f, err, lanes);
+  int st = p->jit.get(p->prog, c->device, prec, o->rng, A, mem, &f, err, lanes, full, tenv);
   if (st != PMC_OK) return fail(c, st, err);
   if (cap) {
     char kb[64];
@@ -617,6 +626,17 @@ int launch_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec, 
   }
   HIP_TRY(c, launch_mc_jit(f, prec, L, grid, block, c->stream));
   return PMC_OK;
+}
+
+// Whole-path capacity of the compiled engine's generated paths for at most
+// `values` (= slots x assets) prices per path: the smallest power of two that
+// holds them, or 0 (the sliding window) above 32 values in FP32 or 16 in
+// FP64 (32 registers either way).
+int full_capacity(const pmc_opts* o, int64_t values, int prec) {
+  if (o->engine == PMC_ENGINE_INTERPRETER || values > (prec ? 16 : 32)) return 0;
+  int cap = 1;
+  while (cap < values) cap <<= 1;
+  return cap;
 }
 
 int engine_used(const pmc_opts* o) {
@@ -637,9 +657,13 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   const int block = o->block ? o->block : 256;
   const uint64_t N = o->n_paths;
   const int n_slots = tb.desc[0].n_slots;
+  const int prec = sizeof(T) == 8 ? 1 : 0;
+  const int full = full_capacity(o, (int64_t)n_slots * A, prec);
   int mode = o->mode;
   if (eval_only) {
     mode = PMC_MODE_TWO_PHASE;
+  } else if (mode == PMC_MODE_AUTO && full > 0) {
+    mode = PMC_MODE_FUSED;   // the whole path is generated once
   } else if (mode == PMC_MODE_AUTO) {
     // fused unless the window would regenerate much more than one path
     std::vector<int32_t> key(tenv, tenv + P.tvars.size());
@@ -677,11 +701,11 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   L.payoff_out = o->payoffs_dev;
   // Timing markers: ev0 (start), evk[0] (generation start, two-phase
   // only), evk[1] (MC kernel start), ev1 (end); each is a queue entry, so
-  // only the ones a reported time needs are recorded.
+  // only the ones a reported time needs are recorded.  (Events attached to
+  // the launches themselves cost more: each such launch waits on its own.)
   HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
   st = prep(c, L, 1, A);
   if (st != PMC_OK) return st;
-  const int prec = sizeof(T) == 8 ? 1 : 0;
   const bool two_phase = mode == PMC_MODE_TWO_PHASE;
   if (two_phase) {
     HIP_TRY(c, hipEventRecord(c->evk[0], c->stream));
@@ -698,7 +722,11 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
     st = launch_engine(c, p, o, prec, n_slots > 0, L, (int)tiles, block, lanes, (int64_t)n_slots * A);
   } else {
     HIP_TRY(c, hipEventRecord(c->evk[1], c->stream));
-    st = launch_engine(c, p, o, prec, false, L, (int)tiles, block, 1, (int64_t)n_slots * A);
+    // whole paths: a kernel generated for this template environment (a
+    // program without template variables has one, the empty one)
+    static const int32_t kNoTenv[1] = {0};
+    st = launch_engine(c, p, o, prec, false, L, (int)tiles, block, 1, (int64_t)n_slots * A, full,
+                       full > 0 ? (tenv ? tenv : kNoTenv) : nullptr);
   }
   if (st != PMC_OK) return st;
   HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
@@ -778,11 +806,16 @@ namespace {
 
 struct BatchPlan {
   McLaunch L;
-  int grid = 0, block = 256, ppt = 1, n_inst = 0, mode = PMC_MODE_FUSED;
+  int grid = 0, block = 256, ppt = 1, n_inst = 0, mode = PMC_MODE_FUSED, full = 0;
+  bool spec = false;            // whole paths, one template environment shared by all instances:
+  std::vector<int32_t> tenv;   // that environment (and a trailing 0)
   std::vector<uint64_t> n_paths;
   std::vector<int> n_slots;
   int64_t path_dates = 0;
 };
+
+// The template environment a batch's kernel is generated for, or null.
+const int32_t* spec_tenv(const BatchPlan& bp) { return bp.spec ? bp.tenv.data() : nullptr; }
 
 template <typename T>
 int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc_gbm* m, const pmc_opts* o,
@@ -837,18 +870,24 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
   L.ppt = ppt;
   L.payoff_out = nullptr;
   bp.L = L;
+  const int full = full_capacity(o, tb.max_dims, sizeof(T) == 8 ? 1 : 0);
+  if (full > 0 && memo.size() == 1) {
+    bp.spec = true;
+    bp.tenv = memo.begin()->first;
+    bp.tenv.push_back(0);
+  }
   int occ = 1;
   if (o->engine == PMC_ENGINE_INTERPRETER) {
     occ = mc_occupancy(sizeof(T) == 8 ? 1 : 0, o->rng, A, P.n_regs, block);
   } else {   // the generated kernel's own register and LDS use
     hipFunction_t f = nullptr;
     std::string err;
-    st = p->jit.get(P, c->device, sizeof(T) == 8 ? 1 : 0, o->rng, A, false, &f, err);
+    st = p->jit.get(P, c->device, sizeof(T) == 8 ? 1 : 0, o->rng, A, false, &f, err, 1, full, spec_tenv(bp));
     if (st != PMC_OK) return fail(c, st, err);
     occ = mc_occupancy_jit(f, block);
   }
   bp.grid = std::max(1, std::min<int>((int)n_work, c->n_cu * occ));
-  bp.block = block; bp.ppt = ppt; bp.n_inst = I;
+  bp.block = block; bp.ppt = ppt; bp.n_inst = I; bp.full = full;
   bp.n_paths.assign(I, N);
   bp.n_slots = tb.n_slots;
   bp.path_dates = tb.path_dates;
@@ -861,7 +900,7 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
 int batch_enqueue(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, const BatchPlan& bp, int prec, int A) {
   int st = prep(c, bp.L, bp.n_inst, A);
   if (st != PMC_OK) return st;
-  return launch_engine(c, p, o, prec, false, bp.L, bp.grid, bp.block);
+  return launch_engine(c, p, o, prec, false, bp.L, bp.grid, bp.block, 1, 0, bp.full, spec_tenv(bp));
 }
 
 int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_opts* o, float* ms_out) {
@@ -869,9 +908,11 @@ int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_op
   const int A = (int)p->prog.assets.size();
   std::ostringstream key;
   key << p->hash << ':' << bp.n_inst << ':' << bp.grid << ':' << bp.block << ':' << bp.ppt << ':' << bp.L.n_work
-      << ':' << prec << ':' << o->rng << ':' << o->engine << ':' << c->blob.p << ':' << c->partial.p << ':' << c->results.dev << ':' << c->counters.p << ':'
+      << ':' << prec << ':' << o->rng << ':' << o->engine << ':' << bp.full << ':' << c->blob.p << ':' << c->partial.p << ':' << c->results.dev << ':' << c->counters.p << ':'
       << c->chol.p << ':' << c->sobol.p << ':' << (const void*)bp.L.sobol_hi << ':' << (const void*)bp.L.desc << ':'
       << (const void*)bp.L.order;
+  key << ':' << bp.spec;
+  for (int32_t v : bp.tenv) key << ' ' << v;   // the kernel variant
   if (c->graph.key != key.str()) {
     if (c->graph.exec) { (void)hipGraphExecDestroy(c->graph.exec); c->graph.exec = nullptr; }
     c->graph.key.clear();
@@ -886,7 +927,7 @@ int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_op
     if (o->engine != PMC_ENGINE_INTERPRETER) {   // compile outside the capture
       hipFunction_t f = nullptr;
       std::string err;
-      int jst = p->jit.get(p->prog, c->device, prec, o->rng, A, false, &f, err);
+      int jst = p->jit.get(p->prog, c->device, prec, o->rng, A, false, &f, err, 1, bp.full, spec_tenv(bp));
       if (jst != PMC_OK) { c->stream = saved; if (own) (void)hipStreamDestroy(cap); return fail(c, jst, err); }
     }
     HIP_TRY(c, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));

@@ -9,29 +9,47 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "ilc.h"
 #include "kernels.h"
 
 namespace pmc {
 
-// Source of the generated payoff evaluator for one program.
-std::string generate_payoff(const Program& P);
+// Source of the generated payoff evaluator for one program: generic (G null:
+// template values, loop shifts and tables read at run time), or for the one
+// template environment whose grid is G (loop iterations written out, fixed
+// reads of the held path).
+std::string generate_payoff(const Program& P, const Grid* G);
+
+// Statements generate_payoff writes for node i under grid G (each loopif
+// iteration written out), capped at cap; kernels for one template
+// environment are generated only up to kMaxUnrolled.
+int64_t unrolled_size(const Program& P, const Grid& G, int i, int64_t cap);
+constexpr int64_t kMaxUnrolled = 4000;
 
 // Compiled kernels of one payoff, keyed by (device, precision, rng, assets,
-// memory source, paths per lane).  Owned by the payoff object.
+// memory source, paths per lane, whole-path capacity).  Owned by the payoff
+// object.
 class JitCache {
  public:
   ~JitCache();
   // Returns the kernel for the variant, compiling it on first use.
-  // lanes > 1 (paths per lane) is for the memory source only.
+  // lanes > 1 (paths per lane) is for the memory source only; full > 0 (a
+  // power of two, at most 32 values) holds each generated path whole; tenv
+  // (with full > 0): the one template environment every instance of the
+  // launch has, for a kernel generated for it; null for the generic kernel.
   int get(const Program& P, int device, int precision, int rng, int n_assets, bool from_memory,
-          hipFunction_t* out, std::string& err, int lanes = 1);
+          hipFunction_t* out, std::string& err, int lanes = 1, int full = 0, const int32_t* tenv = nullptr);
 
  private:
+  // hipRTC compile and module load of one variant; waves > 0 asks for that
+  // many waves per SIMD.
+  int compile(const std::string& src, int precision, int rng, int n_assets, bool mem, int lanes, int full,
+              int waves, hipModule_t* mod, hipFunction_t* fn, std::string& err);
   std::mutex mu_;
   std::map<std::string, std::pair<hipModule_t, hipFunction_t>> k_;
-  std::string src_;  // generated payoff source (built once)
+  std::string src_;  // generic generated payoff source (built once)
 };
 
 }  // namespace pmc

@@ -327,14 +327,20 @@ __device__ __forceinline__ LaneMask<P> vsel(const LaneMask<P>& c, const LaneMask
   return r;
 }
 
-// Generates the path of one lane slot by slot into the window.
-template <typename T, int RNG, int A>
+// Generates the path of one lane slot by slot into the window.  CAP = 0:
+// a window of kWindow values that slides forward and is regenerated from the
+// spot on a backward read (paths of any length).  CAP > 0 (a power of two,
+// at least n_slots * A): the whole path, generated once by prime() before
+// the payoff runs; reads are register selects at a uniform index, and the
+// generation code exists once in the kernel instead of at every read.
+template <typename T, int RNG, int A, int CAP = 0>
 struct GenSource {
+  static_assert(CAP == 0 || (CAP & (CAP - 1)) == 0, "CAP is a power of two");
   using V = T;
   using Mask = bool;
-  static constexpr int kWin = kWindow;
-  using Win = T[kWindow];
-  static constexpr int WS = kWindow / A;   // slots held in the window
+  static constexpr int kWin = CAP > 0 ? CAP : kWindow;
+  using Win = T[kWin];
+  static constexpr int WS = kWindow / A;   // slots held in the sliding window
   T x[A];
   int base;        // first slot in the window (uniform), -1 if empty
   int next_slot;   // next slot to generate (uniform)
@@ -459,10 +465,26 @@ struct GenSource {
     base = s;
   }
 
-  __device__ __forceinline__ T read(T (&win)[kWindow], int slot, int a) {
-    if (slot < base || slot >= base + WS || base < 0) refill(win, slot);
-    const int i = uni((slot - base) * A + a) & (kWindow - 1);
-    return win[i];
+  // The whole path (CAP > 0); nothing for the sliding window.
+  __device__ __forceinline__ void prime(Win& win) {
+    if constexpr (CAP > 0) {
+#pragma unroll 1
+      for (int q = 0; q < n_slots; ++q) {
+        step(q, nullptr, nullptr, 0);
+#pragma unroll
+        for (int a = 0; a < A; ++a) win[(q * A + a) & (CAP - 1)] = M.s0[a] * Num<T>::expv(x[a]);
+      }
+    }
+  }
+
+  __device__ __forceinline__ T read(Win& win, int slot, int a) {
+    if constexpr (CAP > 0) {
+      return win[uni(slot * A + a) & (CAP - 1)];
+    } else {
+      if (slot < base || slot >= base + WS || base < 0) refill(win, slot);
+      const int i = uni((slot - base) * A + a) & (kWindow - 1);
+      return win[i];
+    }
   }
   __device__ __forceinline__ T spot(int a) const { return spotp[a]; }
 };
@@ -522,6 +544,7 @@ struct MemSource {
     }
     base = s;
   }
+  __device__ __forceinline__ void prime(Win&) {}
   __device__ __forceinline__ T read(Win& win, int slot, int a) {
     if (slot < base || slot >= base + WS || base < 0) refill(win, slot);
     const int i = uni((slot - base) * A + a) & (kWindow - 1);
@@ -575,6 +598,7 @@ struct MemSourceLds {
       for (int e = 0; e < P; ++e) lw[i * stride + e] = x[i].v[e];
     base = s;
   }
+  __device__ __forceinline__ void prime(Win&) {}
   __device__ __forceinline__ V read(Win&, int slot, int a) {
     if (slot < base || slot >= base + WS || base < 0) refill(slot);
     const int i = uni((slot - base) * A + a);
@@ -588,12 +612,21 @@ struct MemSourceLds {
 
 // An observable of a model asset on a day: the spot for day <= 0 (flat
 // history), else the simulated price of the day's slot.
+// The grid is given by its first day when dense (else 0: the day map dm),
+// its slot count and its horizon.
+template <class Src>
+__device__ __forceinline__ typename Src::V read_obs(Src& src, typename Src::Win& win, int dense_first,
+                                                    int n_slots, int horizon, kptr<int32_t> dm, int day,
+                                                    int asset) {
+  if (day <= 0) return src.spot(asset);
+  const int s = dense_first > 0 ? min(day - dense_first, n_slots - 1) : uni(dm[min(day, horizon)]);
+  return s < 0 ? src.spot(asset) : src.read(win, s, asset);
+}
+
 template <class Src>
 __device__ __forceinline__ typename Src::V read_obs(Src& src, typename Src::Win& win, const InstDesc& D,
                                                     kptr<int32_t> dm, int day, int asset) {
-  if (day <= 0) return src.spot(asset);
-  const int s = D.dense_first > 0 ? min(day - D.dense_first, D.n_slots - 1) : uni(dm[min(day, D.horizon)]);
-  return s < 0 ? src.spot(asset) : src.read(win, s, asset);
+  return read_obs(src, win, D.dense_first, D.n_slots, D.horizon, dm, day, asset);
 }
 
 // ------------------------------------------------------- interpreter ------
@@ -738,9 +771,12 @@ struct Interp {
 
 // P > 1 (two-phase only): each lane evaluates P consecutive paths; a tile
 // is then P * blockDim paths.
-template <typename T, int RNG, int A, bool MEM, class Eval, int P = 1>
+// FULL > 0: generated paths are held whole (GenSource's CAP; every
+// instance of the launch has n_slots * A <= FULL).
+template <typename T, int RNG, int A, bool MEM, class Eval, int P = 1, int FULL = 0>
 __device__ __forceinline__ void mc_body(const Args<T>& g) {
   static_assert(P == 1 || MEM, "several paths per lane are for stored paths only");
+  static_assert(FULL == 0 || !MEM, "whole-path windows are for generated paths");
   __shared__ double red[8];
   __shared__ int frames_all[4][3 * kMaxLoopDepth];
   __shared__ int item_s;
@@ -791,7 +827,7 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
         src.init(g, D, p);
         v = Eval::template run<T>(g, D, src, frames);
       } else {
-        GenSource<T, RNG, A> src;
+        GenSource<T, RNG, A, FULL> src;
         src.init(g, D, p, lo_tab, has_lo);
         v = Eval::template run<T>(g, D, src, frames);
       }

@@ -52,6 +52,11 @@ CASES = {
     "c1": W.C1,
     "c2_philox": _small(W.C2, rng="philox"),
     "c2d": W.C2D,
+    # 12 dates x 3 assets: more prices than the compiled engine holds whole,
+    # so it slides its window and regenerates on the knock-in's backward reads
+    "c2_long": _small(W.C2, tenv=[11]),
+    # FP64 paths held whole (15 prices in a 16-entry window of register pairs)
+    "c2_f64": _small(W.C2, precision="f64"),
 }
 
 
