@@ -411,10 +411,11 @@ struct GenSource {
   }
 
   // the A words of slot q (words q*A .. q*A+A-1); with the Sobol LDS table
-  // the A loads are issued together
+  // the A loads are issued together (LO: the table is known to be there)
+  template <bool LO = false>
   __device__ __forceinline__ void words(int q, uint32_t (&xw)[A]) {
     const uint32_t w0 = (uint32_t)(q * A);
-    if (RNG == 1 && use_lo) {
+    if (RNG == 1 && (LO || use_lo)) {
 #pragma unroll
       for (int a = 0; a < A; ++a) xw[a] = sobol_hi[w0 + a] ^ lo[(w0 + a) * 64u];
     } else {
@@ -424,9 +425,10 @@ struct GenSource {
   }
 
   // one GBM step to slot q (all assets); optionally record words/normals
+  template <bool LO = false>
   __device__ __forceinline__ void step(int q, uint32_t* wout, T* zout, uint32_t npath) {
     uint32_t xw[A];
-    words(q, xw);
+    words<LO>(q, xw);
     T z[A];
 #pragma unroll
     for (int a = 0; a < A; ++a) {
@@ -465,15 +467,22 @@ struct GenSource {
     base = s;
   }
 
-  // The whole path (CAP > 0); nothing for the sliding window.
+  // The whole path (CAP > 0); nothing for the sliding window.  The loop
+  // is written twice so that the Sobol one with the LDS table carries no
+  // test of the other case.
   __device__ __forceinline__ void prime(Win& win) {
     if constexpr (CAP > 0) {
+      if (RNG == 1 && use_lo) generate_all<true>(win);
+      else generate_all<false>(win);
+    }
+  }
+  template <bool LO>
+  __device__ __forceinline__ void generate_all(Win& win) {
 #pragma unroll 1
-      for (int q = 0; q < n_slots; ++q) {
-        step(q, nullptr, nullptr, 0);
+    for (int q = 0; q < n_slots; ++q) {
+      step<LO>(q, nullptr, nullptr, 0);
 #pragma unroll
-        for (int a = 0; a < A; ++a) win[(q * A + a) & (CAP - 1)] = M.s0[a] * Num<T>::expv(x[a]);
-      }
+      for (int a = 0; a < A; ++a) win[(q * A + a) & (kWin - 1)] = M.s0[a] * Num<T>::expv(x[a]);
     }
   }
 
@@ -497,16 +506,27 @@ struct GenSource {
 // dimensions do not fit.
 constexpr int kSobolLdsDims = 64;
 
+// Each thread loads one dimension's six low direction numbers (one round
+// trip, issued together) and writes four consecutive entries of it; a block
+// of 256 threads covers 16 dimensions per pass.
 template <typename T>
 __device__ __forceinline__ bool sobol_lo_table(const Args<T>& g, uint32_t* tab) {
   if (!g.sobol_hi || g.sobol_dims > kSobolLdsDims) return false;
-  for (int i = threadIdx.x; i < g.sobol_dims * 64; i += blockDim.x) {
-    const uint32_t* v = g.sobol + (size_t)(i >> 6) * 32u;
-    uint32_t acc = 0;
+  const int per_pass = (int)blockDim.x >> 4;   // dimensions per pass
+  for (int w = (int)threadIdx.x >> 4; w < g.sobol_dims; w += per_pass) {
+    const uint32_t* v = g.sobol + (size_t)w * 32u;
+    uint32_t d[6];
 #pragma unroll
-    for (int b = 0; b < 6; ++b)
-      if ((i >> b) & 1) acc ^= v[b];
-    tab[i] = acc;
+    for (int b = 0; b < 6; ++b) d[b] = v[b];
+    const int b0 = ((int)threadIdx.x & 15) * 4;
+    uint32_t base = 0;   // XOR over bits 2..5 of b0
+#pragma unroll
+    for (int b = 2; b < 6; ++b) base ^= d[b] & (0u - (uint32_t)((b0 >> b) & 1));
+    uint32_t* out = tab + w * 64 + b0;
+    out[0] = base;
+    out[1] = base ^ d[0];
+    out[2] = base ^ d[1];
+    out[3] = base ^ d[0] ^ d[1];
   }
   __syncthreads();
   return true;
