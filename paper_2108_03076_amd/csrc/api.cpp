@@ -610,6 +610,7 @@ int launch_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec, 
       grid = std::max(1, std::min(grid, c->n_cu * it->second));
     }
     HIP_TRY(c, launch_mc(prec, o->rng, mem, L, grid, block, c->stream));
+    if (!L.queue) HIP_TRY(c, launch_finish(L.partial, grid, L.result, c->stream));
     return PMC_OK;
   }
   hipFunction_t f = nullptr;
@@ -625,6 +626,8 @@ int launch_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec, 
     grid = std::max(1, std::min(grid, c->n_cu * it->second));
   }
   HIP_TRY(c, launch_mc_jit(f, prec, L, grid, block, c->stream));
+  // one instrument: the per-block partials are summed by a second kernel
+  if (!L.queue) HIP_TRY(c, launch_finish(L.partial, grid, L.result, c->stream));
   return PMC_OK;
 }
 

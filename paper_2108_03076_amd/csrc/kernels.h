@@ -47,6 +47,9 @@ hipError_t launch_pathgen(int precision, int rng, const McLaunch& a, void* paths
 // FP64) into l; status[i] = 0 if matrix i is positive definite, else 1.
 hipError_t launch_prep(const double* a, double* l, int* status, uint32_t* zero, int n_zero, int n, int m,
                        hipStream_t s);
+// Sums partial[0..n) (per-block (sum, sum of squares) of a single-instrument
+// launch) in order into result[0].
+hipError_t launch_finish(const double2* partial, int n, double2* result, hipStream_t s);
 // hi[h][d] = XOR of sobol[d][b] over the set bits b >= 6 of gray(64 h).
 hipError_t launch_sobol_hi(const uint32_t* sobol, uint32_t* hi, int n_rows, int dims, int bits, hipStream_t s);
 // Largest resident blocks per CU for the persistent MC kernel.

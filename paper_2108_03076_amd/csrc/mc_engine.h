@@ -424,6 +424,17 @@ struct GenSource {
     }
   }
 
+  // one GBM step from the slot's normals z and step sizes (dt, sqrt dt)
+  __device__ __forceinline__ void advance(const T (&z)[A], T dt, T sdt) {
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      T wa = T(0);
+#pragma unroll
+      for (int k = 0; k <= a; ++k) wa += M.L[a][k] * z[k];
+      x[a] = x[a] + M.mu[a] * dt + (M.sig[a] * sdt) * wa;
+    }
+  }
+
   // one GBM step to slot q (all assets); optionally record words/normals
   template <bool LO = false>
   __device__ __forceinline__ void step(int q, uint32_t* wout, T* zout, uint32_t npath) {
@@ -437,14 +448,7 @@ struct GenSource {
       if (wout) wout[w * npath + path] = xw[a];
       if (zout) zout[w * npath + path] = z[a];
     }
-    const T dt = slotc[2 * q], sdt = slotc[2 * q + 1];
-#pragma unroll
-    for (int a = 0; a < A; ++a) {
-      T wa = T(0);
-#pragma unroll
-      for (int k = 0; k <= a; ++k) wa += M.L[a][k] * z[k];
-      x[a] = x[a] + M.mu[a] * dt + (M.sig[a] * sdt) * wa;
-    }
+    advance(z, slotc[2 * q], slotc[2 * q + 1]);
   }
 
   // Generates slots up to s + WS - 1 (from the spot again on a backward
@@ -476,11 +480,47 @@ struct GenSource {
       else generate_all<false>(win);
     }
   }
+  // Software pipeline: the slot's scalar loads (step sizes; with the Sobol
+  // table, the wave's high words) are issued one slot ahead, so a slot waits
+  // only for its own LDS reads.  (Scalar and LDS loads share one counter and
+  // scalar ones return out of order: the explicit wait ends this slot's
+  // loads before the next slot's are issued.)
   template <bool LO>
   __device__ __forceinline__ void generate_all(Win& win) {
+    if (n_slots <= 0) return;
+    constexpr bool kTab = RNG == 1 && LO;
+    uint32_t hw[A];
+    T dt = slotc[0], sdt = slotc[1];
+    if constexpr (kTab) {
+#pragma unroll
+      for (int a = 0; a < A; ++a) hw[a] = sobol_hi[a];
+    }
 #pragma unroll 1
     for (int q = 0; q < n_slots; ++q) {
-      step<LO>(q, nullptr, nullptr, 0);
+      uint32_t xw[A];
+      if constexpr (kTab) {
+#pragma unroll
+        for (int a = 0; a < A; ++a) xw[a] = lo[(uint32_t)(q * A + a) * 64u];
+      }
+      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vector-memory and export counts untouched
+      if constexpr (kTab) {
+#pragma unroll
+        for (int a = 0; a < A; ++a) xw[a] ^= hw[a];
+      } else {
+        words<false>(q, xw);
+      }
+      const T cdt = dt, csdt = sdt;
+      const int nq = min(q + 1, n_slots - 1);
+      dt = slotc[2 * nq];
+      sdt = slotc[2 * nq + 1];
+      if constexpr (kTab) {
+#pragma unroll
+        for (int a = 0; a < A; ++a) hw[a] = sobol_hi[nq * A + a];
+      }
+      T z[A];
+#pragma unroll
+      for (int a = 0; a < A; ++a) z[a] = Num<T>::normal_word(xw[a]);
+      advance(z, cdt, csdt);
 #pragma unroll
       for (int a = 0; a < A; ++a) win[(q * A + a) & (kWin - 1)] = M.s0[a] * Num<T>::expv(x[a]);
     }
@@ -894,32 +934,14 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
     }
   }
   if (!g.queue) {
-    // One block reduction, one partial and one counter increment per block
-    // (a returning atomic is a long round trip, paid once per block rather
-    // than per tile); the last block sums the per-block partials in block
-    // order.  Each thread's tiles are fixed by the stride, so the result is
+    // One block reduction and one partial per block; the finishing kernel
+    // that follows on the stream sums the partials in block order.  (A
+    // completion counter instead would serialize: device-scope atomics on
+    // one address from every block of the chip cost about 20 ns each.)
+    // Each thread's tiles are fixed by the stride, so the result is
     // deterministic.
     block_sum2(bs, bss, red);
-    if (threadIdx.x == 0) {
-      g.partial[blockIdx.x] = make_double2(bs, bss);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      last_s = __hip_atomic_fetch_add(&g.done[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-               gridDim.x - 1u;
-    }
-    __syncthreads();
-    if (last_s) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      double a = 0.0, b = 0.0;
-      for (uint32_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
-        const double2 q = g.partial[i];
-        a += q.x; b += q.y;
-      }
-      block_sum2(a, b, red);
-      if (threadIdx.x == 0) {
-        g.result[0] = make_double2(a, b);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: host-mapped memory
-      }
-    }
+    if (threadIdx.x == 0) g.partial[blockIdx.x] = make_double2(bs, bss);
   }
 }
 

@@ -73,6 +73,24 @@ __global__ void k_prep(const double* a, double* l, int* status, uint32_t* zero, 
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: host-mapped memory
 }
 
+// Sums the n per-block partials of a single-instrument launch in block order
+// (a fixed order: deterministic) and writes the instrument's result, which
+// may be host-mapped memory.  One block of kFinishThreads.
+constexpr int kFinishThreads = 256;
+__global__ __launch_bounds__(kFinishThreads) void k_finish(const double2* partial, int n, double2* result) {
+  __shared__ double red[8];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double2 q = partial[i];
+    a += q.x; b += q.y;
+  }
+  block_sum2(a, b, red);
+  if (threadIdx.x == 0) {
+    result[0] = make_double2(a, b);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: host-mapped memory
+  }
+}
+
 __global__ void k_sobol_hi(const uint32_t* v, uint32_t* hi, int n_rows, int dims, int bits) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_rows * dims) return;
@@ -172,6 +190,11 @@ hipError_t launch_prep(const double* a, double* l, int* status, uint32_t* zero, 
                        hipStream_t s) {
   const int t = std::max(n, n_zero);
   hipLaunchKernelGGL(k_prep, dim3((t + 255) / 256), dim3(256), 0, s, a, l, status, zero, n_zero, n, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const double2* partial, int n, double2* result, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, s, partial, n, result);
   return hipGetLastError();
 }
 
