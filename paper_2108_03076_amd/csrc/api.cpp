@@ -149,10 +149,16 @@ extern "C" int pmc_ctx_create(int device, void* stream, pmc_ctx** out) {
   if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail("hipGetDeviceProperties", e);
   c->n_cu = prop.multiProcessorCount;
   c->device_name = prop.gcnArchName;
-  if ((e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess)
+  // Start and intermediate markers only take times: no system-scope cache
+  // write-back and invalidation when they are reached (which would also
+  // leave the following kernel a cold L2).  The end marker, which the host
+  // waits on before reading results, keeps the default fence.
+  if ((e = hipEventCreateWithFlags(&c->ev0, hipEventDisableSystemFence)) != hipSuccess ||
+      (e = hipEventCreate(&c->ev1)) != hipSuccess)
     return hip_fail("hipEventCreate", e);
   for (auto& ev : c->evk)
-    if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail("hipEventCreate", e);
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence)) != hipSuccess)
+      return hip_fail("hipEventCreate", e);
   *out = c.release();
   return PMC_OK;
 }
@@ -702,15 +708,16 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   L.partial = (double2*)c->partial.p;
   L.n_work = (int)tiles;
   L.payoff_out = o->payoffs_dev;
-  // Timing markers: ev0 (start), evk[0] (generation start, two-phase
-  // only), evk[1] (MC kernel start), ev1 (end); each is a queue entry, so
-  // only the ones a reported time needs are recorded.  (Events attached to
-  // the launches themselves cost more: each such launch waits on its own.)
-  HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-  st = prep(c, L, 1, A);
-  if (st != PMC_OK) return st;
+  // Timing markers: ev0 (start), evk[0] (generation start) and evk[1] (MC
+  // kernel start) in the two-phase sequence, ev1 (end); each is a queue
+  // entry, so only the ones a reported time needs are recorded.  (Events
+  // attached to the launches themselves cost more: each such launch waits
+  // on its own.)
   const bool two_phase = mode == PMC_MODE_TWO_PHASE;
+  HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
   if (two_phase) {
+    st = prep(c, L, 1, A);
+    if (st != PMC_OK) return st;
     HIP_TRY(c, hipEventRecord(c->evk[0], c->stream));
     if (given_paths) {
       L.paths = given_paths;
@@ -724,9 +731,13 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
     HIP_TRY(c, hipEventRecord(c->evk[1], c->stream));
     st = launch_engine(c, p, o, prec, n_slots > 0, L, (int)tiles, block, lanes, (int64_t)n_slots * A);
   } else {
-    HIP_TRY(c, hipEventRecord(c->evk[1], c->stream));
-    // whole paths: a kernel generated for this template environment (a
-    // program without template variables has one, the empty one)
+    // Fused: the pricing kernel factors the correlation matrix itself (one
+    // thread per block, into LDS) and reports its status; no preparation
+    // kernel runs.  Whole paths: a kernel generated for this template
+    // environment (a program without template variables has one, the empty
+    // one).
+    L.factor = 1;
+    L.status = status_dev(c, 1);
     static const int32_t kNoTenv[1] = {0};
     st = launch_engine(c, p, o, prec, false, L, (int)tiles, block, 1, (int64_t)n_slots * A, full,
                        full > 0 ? (tenv ? tenv : kNoTenv) : nullptr);
@@ -736,8 +747,12 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   HIP_TRY(c, hipEventSynchronize(c->ev1));
   float ms = 0, gen_ms = 0, eval_ms = 0;
   HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-  if (two_phase) HIP_TRY(c, hipEventElapsedTime(&gen_ms, c->evk[0], c->evk[1]));
-  HIP_TRY(c, hipEventElapsedTime(&eval_ms, c->evk[1], c->ev1));
+  if (two_phase) {
+    HIP_TRY(c, hipEventElapsedTime(&gen_ms, c->evk[0], c->evk[1]));
+    HIP_TRY(c, hipEventElapsedTime(&eval_ms, c->evk[1], c->ev1));
+  } else {
+    eval_ms = ms;   // the pricing kernel and its finishing reduction are the whole sequence
+  }
   st = finish(c, 1, {N}, {n_slots}, mode, ms, out, gen_ms, eval_ms);
   if (st == PMC_OK) out->engine_used = engine_used(o);
   return st;

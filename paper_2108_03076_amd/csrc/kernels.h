@@ -17,6 +17,8 @@ struct McLaunch {
   const void* rtab;           // packed real tables
   const double* chol;         // packed FP64 Cholesky factors
   const double* chol_in;      // packed FP64 correlation matrices (factored on device)
+  int* status;                // per instance: positive-definiteness status (factor = 1)
+  int factor;                 // 1: the MC kernel factors instance 0's matrix per block (no prep)
   const uint32_t* sobol;      // direction numbers [dim][32]
   int sobol_bits;             // bits of the largest path index
   const uint32_t* sobol_hi;   // per-wave high-part table [path/64][dim], or nullptr

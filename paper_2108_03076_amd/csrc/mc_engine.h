@@ -152,6 +152,9 @@ struct Args {
   double2* partial;
   uint32_t* done;        // per instance: finished tiles (zero at launch)
   double2* result;       // per instance: (sum, sum of squares), written by the last tile's block
+  const double* chol_in; // correlation matrices (A x A per instance)
+  int* status;           // per instance: 0, or 1 if the correlation is not positive definite
+  int factor;            // 1: each block factors instance 0's matrix itself (single instrument)
   T* payoff_out;
   const T* paths;
   uint32_t k0, k1;
@@ -187,17 +190,59 @@ template <typename T, int A>
 struct Model {
   T mu[A], sig[A], s0[A];
   T L[A][A];
-  __device__ __forceinline__ void load(const Args<T>& g, const InstDesc& D) {
+  // The factor comes from the prepared table, or (own) from the block's own
+  // factorisation, held in scalar registers (lf, row-major).
+  __device__ __forceinline__ void load(const Args<T>& g, const InstDesc& D, const T* lf, bool own) {
     kptr<T> m = K(g.rtab) + D.model_off;
 #pragma unroll
     for (int a = 0; a < A; ++a) { mu[a] = m[a]; sig[a] = m[A + a]; s0[a] = m[2 * A + a]; }
-    kptr<double> l = K(g.chol) + D.chol_off;
+    if (own) {
 #pragma unroll
-    for (int i = 0; i < A; ++i)
+      for (int i = 0; i < A; ++i)
 #pragma unroll
-      for (int j = 0; j < A; ++j) L[i][j] = (T)l[i * A + j];
+        for (int j = 0; j < A; ++j) L[i][j] = lf[i * A + j];
+    } else {
+      kptr<double> l = K(g.chol) + D.chol_off;
+#pragma unroll
+      for (int i = 0; i < A; ++i)
+#pragma unroll
+        for (int j = 0; j < A; ++j) L[i][j] = (T)l[i * A + j];
+    }
   }
 };
+
+// A wave-uniform value, marked as such (kept in scalar registers).
+__device__ __forceinline__ float uniform_value(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uniform_value(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll)), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// FP64 Cholesky-Banachiewicz (row by row) of the m x m matrix a into the
+// lower triangle of l (upper part zeroed); false if a is not positive
+// definite.  Used by the preparation kernel and by blocks that factor their
+// instrument's matrix themselves, so both give the same factor bit for bit.
+template <typename PA, typename PL>
+__device__ __forceinline__ bool chol_factor(PA a, PL l, int m) {
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < m; ++c) l[r * m + c] = 0.0;
+  for (int r = 0; r < m; ++r) {
+    for (int c = 0; c <= r; ++c) {
+      double s = a[r * m + c];
+      for (int k = 0; k < c; ++k) s -= l[r * m + k] * l[c * m + k];
+      if (r == c) {
+        if (!(s > 0.0)) return false;
+        l[r * m + r] = sqrt(s);
+      } else {
+        l[r * m + c] = s / l[c * m + c];
+      }
+    }
+  }
+  return true;
+}
 
 // ------------------------------------------------------ lane vectors -----
 // The two-phase evaluator may give each lane P consecutive paths: the
@@ -358,7 +403,7 @@ struct GenSource {
   Model<T, A> M;
 
   __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p, lptr<uint32_t> lo_tab,
-                                       bool has_lo) {
+                                       bool has_lo, const T* l_own = nullptr, bool own = false) {
     path = p; gray = p ^ (p >> 1);
     use_lo = RNG == 1 && has_lo;
     lo = lo_tab + (gray & 63u);
@@ -373,7 +418,7 @@ struct GenSource {
       const uint32_t h = (uint32_t)uni((int)(p >> 6));
       sobol_hi = K(g.sobol_hi) + (size_t)h * (size_t)sobol_dims;
     }
-    M.load(g, d);
+    M.load(g, d, l_own, own);
     slotc = K(g.rtab) + d.slot_off;
     spotp = K(g.rtab) + d.model_off + 2 * A;
     base = -1; next_slot = 0; blk = 0xFFFFFFFFu;
@@ -842,12 +887,34 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
   __shared__ int item_s;
   __shared__ int last_s;
   int* frames = frames_all[threadIdx.x >> 6];
+  // A single fused instrument: one thread of each block factors the
+  // correlation matrix into LDS (block 0 also reports whether it is positive
+  // definite) while the others build the Sobol table; after the barrier that
+  // publishes both, every thread keeps the factor in scalar registers.  (The
+  // choice is an explicit flag, never a null test of an LDS pointer: an LDS
+  // array may sit at address 0.)
+  constexpr int kLA = A > 0 ? A * A : 1;
+  T l_own[kLA] = {};   // the block's factor in working precision (wave-uniform)
+  const bool own = !MEM && g.factor != 0;
+  __shared__ double chol_sh[kLA];
+  if (own && threadIdx.x == 0) {
+    const bool ok = chol_factor(K(g.chol_in), chol_sh, A);
+    if (blockIdx.x == 0) {
+      g.status[0] = ok ? 0 : 1;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: host-mapped memory
+    }
+  }
   bool has_lo = false;
   lptr<uint32_t> lo_tab = nullptr;
   if constexpr (RNG == 1 && !MEM) {
     __shared__ uint32_t sob_lo[kSobolLdsDims * 64];
-    has_lo = sobol_lo_table(g, sob_lo);
+    has_lo = sobol_lo_table(g, sob_lo);   // ends with a barrier when it builds the table
     lo_tab = (lptr<uint32_t>)sob_lo;
+  }
+  if (own) {
+    if (!has_lo) __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kLA; ++k) l_own[k] = uniform_value((T)chol_sh[k]);
   }
   lwptr<T> mem_win = nullptr;
   if constexpr (MEM && P > 1) {
@@ -888,7 +955,7 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
         v = Eval::template run<T>(g, D, src, frames);
       } else {
         GenSource<T, RNG, A, FULL> src;
-        src.init(g, D, p, lo_tab, has_lo);
+        src.init(g, D, p, lo_tab, has_lo, l_own, own);
         v = Eval::template run<T>(g, D, src, frames);
       }
 #pragma unroll

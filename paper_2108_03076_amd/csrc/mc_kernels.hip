@@ -28,6 +28,7 @@ Args<T> typed(const McLaunch& a) {
   g.rtab = (const T*)a.rtab; g.chol = a.chol; g.sobol = a.sobol; g.sobol_bits = a.sobol_bits;
   g.order = a.order; g.tiles = a.tiles; g.n_work = a.n_work; g.queue = a.queue; g.partial = a.partial;
   g.done = a.done; g.result = a.result;
+  g.chol_in = a.chol_in; g.status = a.status; g.factor = a.factor;
   g.payoff_out = (T*)a.payoff_out; g.paths = (const T*)a.paths; g.k0 = a.k0; g.k1 = a.k1;
   g.ppt = a.ppt; g.n_assets = a.n_assets;
   g.sobol_hi = a.sobol_hi; g.sobol_dims = a.sobol_dims;
@@ -52,23 +53,7 @@ __global__ void k_prep(const double* a, double* l, int* status, uint32_t* zero, 
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_zero) zero[i] = 0u;
   if (i >= n) return;
-  const double* A_ = a + (size_t)i * m * m;
-  double* L = l + (size_t)i * m * m;
-  int ok = 1;
-  for (int r = 0; r < m; ++r)
-    for (int c = 0; c < m; ++c) L[r * m + c] = 0.0;
-  for (int r = 0; r < m && ok; ++r) {
-    for (int c = 0; c <= r; ++c) {
-      double s = A_[r * m + c];
-      for (int k = 0; k < c; ++k) s -= L[r * m + k] * L[c * m + k];
-      if (r == c) {
-        if (!(s > 0.0)) { ok = 0; break; }
-        L[r * m + r] = sqrt(s);
-      } else {
-        L[r * m + c] = s / L[c * m + c];
-      }
-    }
-  }
+  const bool ok = chol_factor(a + (size_t)i * m * m, l + (size_t)i * m * m, m);
   status[i] = ok ? 0 : 1;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: host-mapped memory
 }
