@@ -39,6 +39,14 @@ struct McLaunch {
   int n_regs;                 // registers the program uses (selects the file size)
 };
 
+// A resolved Monte Carlo launch: a run-time compiled kernel (jit) or the
+// static interpreter kernel of (prec, rng, mem), and the grid.
+struct EngineLaunch {
+  hipFunction_t f = nullptr;
+  bool jit = false, mem = false;
+  int prec = 0, rng = 0, grid = 0, block = 0;
+};
+
 hipError_t launch_mc(int precision, int rng, bool from_memory, const McLaunch& a, int grid, int block,
                      hipStream_t s);
 // Launch of a run-time compiled Monte Carlo kernel (generated payoff).

@@ -899,10 +899,9 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
   __shared__ double chol_sh[kLA];
   if (own && threadIdx.x == 0) {
     const bool ok = chol_factor(K(g.chol_in), chol_sh, A);
-    if (blockIdx.x == 0) {
-      g.status[0] = ok ? 0 : 1;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: host-mapped memory
-    }
+    // (host-mapped memory, read after the host's wait on the launch's end
+    // event, whose system-scope release publishes it)
+    if (blockIdx.x == 0) g.status[0] = ok ? 0 : 1;
   }
   bool has_lo = false;
   lptr<uint32_t> lo_tab = nullptr;

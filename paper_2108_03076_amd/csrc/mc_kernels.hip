@@ -60,7 +60,10 @@ __global__ void k_prep(const double* a, double* l, int* status, uint32_t* zero, 
 
 // Sums the n per-block partials of a single-instrument launch in block order
 // (a fixed order: deterministic) and writes the instrument's result, which
-// may be host-mapped memory.  One block of kFinishThreads.
+// may be host-mapped memory; the host reads it after waiting on an event
+// recorded behind this kernel, whose system-scope release publishes it (no
+// fence here: an in-kernel one writes back the whole L2).  One block of
+// kFinishThreads.
 constexpr int kFinishThreads = 256;
 __global__ __launch_bounds__(kFinishThreads) void k_finish(const double2* partial, int n, double2* result) {
   __shared__ double red[8];
@@ -70,10 +73,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(const double2* partia
     a += q.x; b += q.y;
   }
   block_sum2(a, b, red);
-  if (threadIdx.x == 0) {
-    result[0] = make_double2(a, b);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: host-mapped memory
-  }
+  if (threadIdx.x == 0) result[0] = make_double2(a, b);
 }
 
 __global__ void k_sobol_hi(const uint32_t* v, uint32_t* hi, int n_rows, int dims, int bits) {
