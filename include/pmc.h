@@ -196,7 +196,10 @@ typedef struct pmc_result {
   int mode_used;
   double ms;          /* device time of the whole kernel sequence (HIP events) */
   double gen_ms;      /* two-phase only: path generation kernel */
-  double eval_ms;     /* the Monte Carlo / payoff kernel */
+  double eval_ms;     /* the Monte Carlo / payoff kernel (fused single pricing:
+                         from the start marker to the pricing kernel's end,
+                         before the one-block finishing reduction; two-phase:
+                         the evaluator and its reduction) */
   int engine_used;    /* PMC_ENGINE_INTERPRETER or PMC_ENGINE_COMPILED */
 } pmc_result;
 

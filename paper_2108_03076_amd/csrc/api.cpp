@@ -90,7 +90,7 @@ struct pmc_ctx {
   std::vector<uint8_t> last_upload;   // bytes the blob holds (skip identical uploads)
   HostPinned staging;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  hipEvent_t evk[3] = {nullptr, nullptr, nullptr};   // around the generation and MC kernels
+  hipEvent_t evk[3] = {nullptr, nullptr, nullptr};   // around the generation and pricing kernels
   int sobol_dims = 0;
   int n_cu = 0;
   std::string device_name;
@@ -675,11 +675,15 @@ int resolve_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec,
 }
 
 // Enqueues a resolved launch; one instrument (no work queue): the
-// per-block partials are summed by a second kernel.
-int run_engine(pmc_ctx* c, const EngineLaunch& e, const McLaunch& L) {
+// per-block partials are summed by a second kernel, and `mid` (optional)
+// marks the end of the pricing kernel itself.
+int run_engine(pmc_ctx* c, const EngineLaunch& e, const McLaunch& L, hipEvent_t mid = nullptr) {
   if (e.jit) HIP_TRY(c, launch_mc_jit(e.f, e.prec, L, e.grid, e.block, c->stream));
   else HIP_TRY(c, launch_mc(e.prec, e.rng, e.mem, L, e.grid, e.block, c->stream));
-  if (!L.queue) HIP_TRY(c, launch_finish(L.partial, e.grid, L.result, c->stream));
+  if (!L.queue) {
+    if (mid) HIP_TRY(c, hipEventRecord(mid, c->stream));
+    HIP_TRY(c, launch_finish(L.partial, e.grid, L.result, c->stream));
+  }
   return PMC_OK;
 }
 
@@ -769,7 +773,7 @@ int complete_single(pmc_ctx* c, uint64_t N, int n_slots, int mode, bool two_phas
     HIP_TRY(c, hipEventElapsedTime(&gen_ms, c->evk[0], c->evk[1]));
     HIP_TRY(c, hipEventElapsedTime(&eval_ms, c->evk[1], c->ev1));
   } else {
-    eval_ms = ms;   // the pricing kernel and its finishing reduction are the whole sequence
+    HIP_TRY(c, hipEventElapsedTime(&eval_ms, c->ev0, c->evk[2]));   // the pricing kernel, before k_finish
   }
   const int st = finish(c, 1, &N, &n_slots, mode, ms, out, gen_ms, eval_ms);
   if (st == PMC_OK) out->engine_used = engine;
@@ -786,7 +790,7 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   if (keyed && prepared_hit(c)) {
     const auto& pr = c->prepared;
     HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-    int st = run_engine(c, pr.e, pr.L);
+    int st = run_engine(c, pr.e, pr.L, c->evk[2]);
     if (st != PMC_OK) return st;
     return complete_single(c, pr.n_paths, pr.n_slots, PMC_MODE_FUSED, false, pr.engine, out);
   }
@@ -844,8 +848,9 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   L.n_work = (int)tiles;
   L.payoff_out = o->payoffs_dev;
   // Timing markers: ev0 (start), evk[0] (generation start) and evk[1] (MC
-  // kernel start) in the two-phase sequence, ev1 (end); each is a queue
-  // entry, so only the ones a reported time needs are recorded.  (Events
+  // kernel start) in the two-phase sequence, evk[2] (pricing kernel end,
+  // before its finishing reduction) in the fused one, ev1 (end); each is a
+  // queue entry, so only the ones a reported time needs are recorded.  (Events
   // attached to the launches themselves cost more: each such launch waits
   // on its own.)
   const bool two_phase = mode == PMC_MODE_TWO_PHASE;
@@ -890,7 +895,7 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
       pr.engine = engine_used(o);
       pr.valid = true;
     }
-    st = run_engine(c, e, L);
+    st = run_engine(c, e, L, c->evk[2]);
   }
   if (st != PMC_OK) return st;
   return complete_single(c, N, n_slots, mode, two_phase, engine_used(o), out);
