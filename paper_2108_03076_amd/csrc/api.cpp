@@ -252,13 +252,15 @@ extern "C" int pmc_payoff_source(const pmc_payoff* p, const int32_t* tenv, char*
   if (!p || !len) return PMC_E_ARG;
   pmc::Grid g;
   const pmc::Grid* gp = nullptr;
+  bool fixed = false;
   if (tenv) {
     std::string err;
     const int st = pmc::plan(p->prog, tenv, g, err);
     if (st != PMC_OK) return st;
-    if (pmc::unrolled_size(p->prog, g, p->prog.root, pmc::kMaxUnrolled + 1) <= pmc::kMaxUnrolled) gp = &g;
+    gp = &g;
+    fixed = pmc::unrolled_size(p->prog, g, p->prog.root, pmc::kMaxUnrolled + 1) <= pmc::kMaxUnrolled;
   }
-  const std::string s = std::string(pmc::kEngineSource) + "\n" + generate_payoff(p->prog, gp);
+  const std::string s = std::string(pmc::kEngineSource) + "\n" + generate_payoff(p->prog, gp, fixed);
   *len = s.size();
   if (buf && cap) {
     const size_t n = std::min(cap - 1, s.size());
@@ -854,6 +856,10 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   // attached to the launches themselves cost more: each such launch waits
   // on its own.)
   const bool two_phase = mode == PMC_MODE_TWO_PHASE;
+  // the pricing kernel is generated for this template environment (a
+  // program without template variables has one, the empty one)
+  static const int32_t kNoTenv[1] = {0};
+  const int32_t* env = tenv ? tenv : kNoTenv;
   HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
   if (two_phase) {
     st = prep(c, L, 1, A);
@@ -869,19 +875,15 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
     }
     if (n_slots == 0) L.paths = nullptr;
     HIP_TRY(c, hipEventRecord(c->evk[1], c->stream));
-    st = launch_engine(c, p, o, prec, n_slots > 0, L, (int)tiles, block, lanes, (int64_t)n_slots * A);
+    st = launch_engine(c, p, o, prec, n_slots > 0, L, (int)tiles, block, lanes, (int64_t)n_slots * A, 0, env);
   } else {
     // Fused: the pricing kernel factors the correlation matrix itself (one
     // thread per block, into LDS) and reports its status; no preparation
-    // kernel runs.  Whole paths: a kernel generated for this template
-    // environment (a program without template variables has one, the empty
-    // one).
+    // kernel runs.
     L.factor = 1;
     L.status = status_dev(c, 1);
-    static const int32_t kNoTenv[1] = {0};
     EngineLaunch e;
-    st = resolve_engine(c, p, o, prec, false, L, (int)tiles, block, 1, (int64_t)n_slots * A, full,
-                        full > 0 ? (tenv ? tenv : kNoTenv) : nullptr, e);
+    st = resolve_engine(c, p, o, prec, false, L, (int)tiles, block, 1, (int64_t)n_slots * A, full, env, e);
     if (st != PMC_OK) return st;
     if (keyed) {   // the next identical call can reuse all of this
       auto& pr = c->prepared;
@@ -968,7 +970,7 @@ namespace {
 struct BatchPlan {
   McLaunch L;
   int grid = 0, block = 256, ppt = 1, n_inst = 0, mode = PMC_MODE_FUSED, full = 0;
-  bool spec = false;            // whole paths, one template environment shared by all instances:
+  bool spec = false;            // one template environment shared by all instances:
   std::vector<int32_t> tenv;   // that environment (and a trailing 0)
   std::vector<uint64_t> n_paths;
   std::vector<int> n_slots;
@@ -1032,7 +1034,7 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
   L.payoff_out = nullptr;
   bp.L = L;
   const int full = full_capacity(o, tb.max_dims, sizeof(T) == 8 ? 1 : 0);
-  if (full > 0 && memo.size() == 1) {
+  if (memo.size() == 1) {
     bp.spec = true;
     bp.tenv = memo.begin()->first;
     bp.tenv.push_back(0);

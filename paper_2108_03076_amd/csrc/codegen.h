@@ -17,10 +17,11 @@
 namespace pmc {
 
 // Source of the generated payoff evaluator for one program: generic (G null:
-// template values, loop shifts and tables read at run time), or for the one
-// template environment whose grid is G (loop iterations written out, fixed
-// reads of the held path).
-std::string generate_payoff(const Program& P, const Grid* G);
+// template values, grid, loop shifts and tables read at run time), or for
+// the one template environment whose grid is G (its values constants; with
+// `fixed`, loop iterations written out and the held path read at fixed
+// registers).
+std::string generate_payoff(const Program& P, const Grid* G, bool fixed);
 
 // Statements generate_payoff writes for node i under grid G (each loopif
 // iteration written out), capped at cap; kernels for one template
@@ -36,9 +37,9 @@ class JitCache {
   ~JitCache();
   // Returns the kernel for the variant, compiling it on first use.
   // lanes > 1 (paths per lane) is for the memory source only; full > 0 (a
-  // power of two, at most 32 values) holds each generated path whole; tenv
-  // (with full > 0): the one template environment every instance of the
-  // launch has, for a kernel generated for it; null for the generic kernel.
+  // power of two, at most 32 values) holds each generated path whole; tenv:
+  // the one template environment every instance of the launch has, for a
+  // kernel generated for it; null for the generic kernel.
   int get(const Program& P, int device, int precision, int rng, int n_assets, bool from_memory,
           hipFunction_t* out, std::string& err, int lanes = 1, int full = 0, const int32_t* tenv = nullptr);
 

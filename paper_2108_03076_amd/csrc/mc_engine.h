@@ -665,7 +665,7 @@ struct MemSource {
 // register copies of a loop-carried window).
 template <typename T>
 using lwptr = __attribute__((address_space(3))) T*;
-constexpr int kLdsWin = 8;   // window entries per lane
+constexpr int kLdsWin = 4;   // window entries per lane
 
 template <typename T, int A, int P>
 struct MemSourceLds {
