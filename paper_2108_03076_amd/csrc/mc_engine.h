@@ -261,14 +261,17 @@ struct alignas(sizeof(T) * P) LaneVec {
     for (int i = 0; i < P; ++i) v[i] = x;
   }
 };
+// P decisions of one lane as bits 0..P-1 of a vector register: their logic
+// is one vector instruction for all P paths (as P separate booleans it
+// became P 64-bit lane masks on the scalar unit, which bounds the stored-path
+// evaluator).
 template <int P>
 struct LaneMask {
-  bool b[P];
+  static constexpr uint32_t kAll = (1u << P) - 1u;
+  uint32_t m;
   LaneMask() = default;
-  __device__ __forceinline__ LaneMask(bool x) {
-#pragma unroll
-    for (int i = 0; i < P; ++i) b[i] = x;
-  }
+  __device__ __forceinline__ LaneMask(bool x) : m(x ? kAll : 0u) {}
+  __device__ __forceinline__ bool bit(int i) const { return (m >> i) & 1u; }
 };
 template <bool B, class X, class Y> struct pick_t { using type = X; };
 template <class X, class Y> struct pick_t<false, X, Y> { using type = Y; };
@@ -306,7 +309,8 @@ PMC_VEC_BINARY(vmax, fmax(a, b))
   template <typename T, int P>                                                                      \
   __device__ __forceinline__ LaneMask<P> NAME(const LaneVec<T, P>& x, const LaneVec<T, P>& y) {     \
     LaneMask<P> r;                                                                                  \
-    _Pragma("unroll") for (int i = 0; i < P; ++i) r.b[i] = x.v[i] OP y.v[i];                        \
+    r.m = 0u;                                                                                       \
+    _Pragma("unroll") for (int i = 0; i < P; ++i) r.m |= (x.v[i] OP y.v[i]) ? (1u << i) : 0u;       \
     return r;                                                                                       \
   }
 PMC_VEC_COMPARE(vlt, <)
@@ -329,46 +333,34 @@ __device__ __forceinline__ bool vall(bool a) { return __all(a); }
 template <typename T> __device__ __forceinline__ T vsel(bool c, T a, T b) { return c ? a : b; }
 template <int P> __device__ __forceinline__ LaneMask<P> vnot(const LaneMask<P>& a) {
   LaneMask<P> r;
-#pragma unroll
-  for (int i = 0; i < P; ++i) r.b[i] = !a.b[i];
+  r.m = a.m ^ LaneMask<P>::kAll;
   return r;
 }
 template <int P> __device__ __forceinline__ LaneMask<P> vand(const LaneMask<P>& a, const LaneMask<P>& b) {
   LaneMask<P> r;
-#pragma unroll
-  for (int i = 0; i < P; ++i) r.b[i] = a.b[i] && b.b[i];
+  r.m = a.m & b.m;
   return r;
 }
 template <int P> __device__ __forceinline__ LaneMask<P> vor(const LaneMask<P>& a, const LaneMask<P>& b) {
   LaneMask<P> r;
-#pragma unroll
-  for (int i = 0; i < P; ++i) r.b[i] = a.b[i] || b.b[i];
+  r.m = a.m | b.m;
   return r;
 }
-template <int P> __device__ __forceinline__ bool vany(const LaneMask<P>& a) {
-  bool x = false;
-#pragma unroll
-  for (int i = 0; i < P; ++i) x = x || a.b[i];
-  return __any(x);
-}
+template <int P> __device__ __forceinline__ bool vany(const LaneMask<P>& a) { return __any(a.m != 0u); }
 template <int P> __device__ __forceinline__ bool vall(const LaneMask<P>& a) {
-  bool x = true;
-#pragma unroll
-  for (int i = 0; i < P; ++i) x = x && a.b[i];
-  return __all(x);
+  return __all(a.m == LaneMask<P>::kAll);
 }
 template <typename T, int P>
 __device__ __forceinline__ LaneVec<T, P> vsel(const LaneMask<P>& c, const LaneVec<T, P>& a, const LaneVec<T, P>& b) {
   LaneVec<T, P> r;
 #pragma unroll
-  for (int i = 0; i < P; ++i) r.v[i] = c.b[i] ? a.v[i] : b.v[i];
+  for (int i = 0; i < P; ++i) r.v[i] = c.bit(i) ? a.v[i] : b.v[i];
   return r;
 }
 template <int P>
 __device__ __forceinline__ LaneMask<P> vsel(const LaneMask<P>& c, const LaneMask<P>& a, const LaneMask<P>& b) {
   LaneMask<P> r;
-#pragma unroll
-  for (int i = 0; i < P; ++i) r.b[i] = c.b[i] ? a.b[i] : b.b[i];
+  r.m = (c.m & a.m) | (~c.m & b.m & LaneMask<P>::kAll);
   return r;
 }
 
