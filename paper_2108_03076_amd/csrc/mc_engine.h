@@ -364,6 +364,14 @@ __device__ __forceinline__ LaneMask<P> vsel(const LaneMask<P>& c, const LaneMask
   return r;
 }
 
+// Window bookkeeping of the sliding path sources: base is the window's first
+// slot, kNoWindow while it is empty; a slot outside [base, base + ws) takes
+// one unsigned comparison (slots are below 2^30).
+constexpr int kNoWindow = -(1 << 30);
+__device__ __forceinline__ bool outside(int slot, int base, int ws) {
+  return (uint32_t)(slot - base) >= (uint32_t)ws;
+}
+
 // Generates the path of one lane slot by slot into the window.  CAP = 0:
 // a window of kWindow values that slides forward and is regenerated from the
 // spot on a backward read (paths of any length).  CAP > 0 (a power of two,
@@ -413,7 +421,7 @@ struct GenSource {
     M.load(g, d, l_own, own);
     slotc = K(g.rtab) + d.slot_off;
     spotp = K(g.rtab) + d.model_off + 2 * A;
-    base = -1; next_slot = 0; blk = 0xFFFFFFFFu;
+    base = kNoWindow; next_slot = 0; blk = 0xFFFFFFFFu;
 #pragma unroll
     for (int a = 0; a < A; ++a) x[a] = T(0);
   }
@@ -567,7 +575,7 @@ struct GenSource {
     if constexpr (CAP > 0) {
       return win[uni(slot * A + a) & (CAP - 1)];
     } else {
-      if (slot < base || slot >= base + WS || base < 0) refill(win, slot);
+      if (outside(slot, base, WS)) refill(win, slot);
       const int i = uni((slot - base) * A + a) & (kWindow - 1);
       return win[i];
     }
@@ -625,7 +633,7 @@ struct MemSource {
   kptr<T> spotp;
 
   __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p) {
-    path = p; n_paths = d.n_paths; n_slots = d.n_slots; base = -1;
+    path = p; n_paths = d.n_paths; n_slots = d.n_slots; base = kNoWindow;
     paths = g.paths;
     spotp = K(g.rtab) + d.model_off + 2 * A;
   }
@@ -643,7 +651,7 @@ struct MemSource {
   }
   __device__ __forceinline__ void prime(Win&) {}
   __device__ __forceinline__ T read(Win& win, int slot, int a) {
-    if (slot < base || slot >= base + WS || base < 0) refill(win, slot);
+    if (outside(slot, base, WS)) refill(win, slot);
     const int i = uni((slot - base) * A + a) & (kWindow - 1);
     return win[i];
   }
@@ -673,7 +681,7 @@ struct MemSourceLds {
   kptr<T> spotp;
 
   __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p, lwptr<T> lds) {
-    path = p; n_paths = d.n_paths; n_slots = d.n_slots; base = -1;
+    path = p; n_paths = d.n_paths; n_slots = d.n_slots; base = kNoWindow;
     paths = g.paths;
     stride = (int)blockDim.x * P;
     lw = lds + threadIdx.x * P;
@@ -697,7 +705,7 @@ struct MemSourceLds {
   }
   __device__ __forceinline__ void prime(Win&) {}
   __device__ __forceinline__ V read(Win&, int slot, int a) {
-    if (slot < base || slot >= base + WS || base < 0) refill(slot);
+    if (outside(slot, base, WS)) refill(slot);
     const int i = uni((slot - base) * A + a);
     V r;
 #pragma unroll
@@ -711,12 +719,18 @@ struct MemSourceLds {
 // history), else the simulated price of the day's slot.
 // The grid is given by its first day when dense (else 0: the day map dm),
 // its slot count and its horizon.
+// (A dense grid starts on a day >= 1, so its slot test also covers day <= 0.)
 template <class Src>
 __device__ __forceinline__ typename Src::V read_obs(Src& src, typename Src::Win& win, int dense_first,
                                                     int n_slots, int horizon, kptr<int32_t> dm, int day,
                                                     int asset) {
-  if (day <= 0) return src.spot(asset);
-  const int s = dense_first > 0 ? min(day - dense_first, n_slots - 1) : uni(dm[min(day, horizon)]);
+  int s;
+  if (dense_first > 0) {
+    s = min(day - dense_first, n_slots - 1);
+  } else {
+    if (day <= 0) return src.spot(asset);
+    s = uni(dm[min(day, horizon)]);
+  }
   return s < 0 ? src.spot(asset) : src.read(win, s, asset);
 }
 
