@@ -687,15 +687,28 @@ struct MemSourceLds {
     lw = lds + threadIdx.x * P;
     spotp = K(g.rtab) + d.model_off + 2 * A;
   }
+  // Slots s .. s+WS-1 (clamped to the last): one 64-bit row offset, then
+  // the others by adding the per-slot row stride (a window inside the path
+  // needs no clamping).
   __device__ __forceinline__ void refill(int s) {
     const int last = n_slots - 1;
+    const size_t row = (size_t)A * n_paths;   // elements per slot
     V x[WS * A];
+    if (s + WS - 1 <= last) {
+      const T* p0 = paths + (size_t)s * row + path;
 #pragma unroll
-    for (int j = 0; j < WS; ++j) {
-      const int q = min(s + j, last);
+      for (int j = 0; j < WS; ++j)
 #pragma unroll
-      for (int a = 0; a < A; ++a)
-        x[j * A + a] = *reinterpret_cast<const V*>(paths + ((size_t)q * A + a) * n_paths + path);
+        for (int a = 0; a < A; ++a)
+          x[j * A + a] = *reinterpret_cast<const V*>(p0 + (size_t)j * row + (size_t)a * n_paths);
+    } else {
+#pragma unroll
+      for (int j = 0; j < WS; ++j) {
+        const int q = min(s + j, last);
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+          x[j * A + a] = *reinterpret_cast<const V*>(paths + (size_t)q * row + (size_t)a * n_paths + path);
+      }
     }
 #pragma unroll
     for (int i = 0; i < WS * A; ++i)
