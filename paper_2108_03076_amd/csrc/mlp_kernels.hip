@@ -236,50 +236,61 @@ __global__ void k_pack(const float* __restrict__ master, int out, int in, int ou
 }
 
 // Fused inference for width 256: a block carries 128 samples through the
-// four layers.  Wave w owns rows 32w .. 32w+31 of the block's activations,
-// kept in LDS as BF16 between layers (rows padded by 8 elements, so the 16
-// rows of a half-wave's A-fragment reads fall on distinct banks), and
-// computes all 256 columns of its rows: eight 32 x 32 MFMA tiles share each
-// A fragment, the weights stream from L2.  The k order, the MFMA instruction
-// and the epilogues are those of the per-layer kernels, so the outputs are
-// the same bit for bit.
+// four layers, their activations kept in LDS as BF16 between layers (rows
+// padded by 8 elements, so the 16 rows of a half-wave's A-fragment reads
+// fall on distinct banks).  Wave w computes output columns 64w .. 64w+63
+// of all 128 rows: per k step it loads its two weight fragments once (each
+// weight is read once per block, not once per wave) and four activation
+// fragments from LDS, for eight 32 x 32 MFMA tiles.  The k order, the MFMA
+// instruction and the epilogues are those of the per-layer kernels, so the
+// outputs are the same bit for bit.
 constexpr int kInferRows = 128;
 constexpr int kInferW = 256;
 constexpr int kInferLd = kInferW + 8;
 
+// acc[rt][c]: rows 32 rt .. 32 rt + 31, columns 32 (2w + c) .. + 31; column
+// tiles at or beyond ntiles (the padded output layer) are skipped.
 template <int K>
-__device__ __forceinline__ void infer_layer(const __bf16* my, const __bf16* __restrict__ Wl, int ntiles,
-                                            f32x16 (&acc)[8]) {
-  const int lane = threadIdx.x & 63, r = lane & 31, kh = (lane >> 5) * 8;
+__device__ __forceinline__ void infer_layer(const __bf16* act, const __bf16* __restrict__ Wl, int ntiles,
+                                            f32x16 (&acc)[4][2]) {
+  const int lane = threadIdx.x & 63, r = lane & 31, kh = (lane >> 5) * 8, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int t = 0; t < 8; ++t)
+  for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
-#pragma unroll 4
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[rt][c][e] = 0.0f;
+  if (2 * w >= ntiles) return;
+#pragma unroll 2
   for (int k = 0; k < K; k += 16) {
-    const bf16x8 a = *reinterpret_cast<const bf16x8*>(my + r * kInferLd + k + kh);
+    bf16x8 b[2];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      if (t < ntiles) {
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(Wl + (size_t)(32 * t + r) * K + k + kh);
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
-      }
+    for (int c = 0; c < 2; ++c)
+      if (2 * w + c < ntiles) b[c] = *reinterpret_cast<const bf16x8*>(Wl + (size_t)(32 * (2 * w + c) + r) * K + k + kh);
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(act + (32 * rt + r) * kInferLd + k + kh);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        if (2 * w + c < ntiles) acc[rt][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[c], acc[rt][c], 0, 0, 0);
     }
   }
 }
 
-__device__ __forceinline__ void infer_hidden_epilogue(__bf16* my, const float* __restrict__ bias,
-                                                      const f32x16 (&acc)[8]) {
-  const int lane = threadIdx.x & 63, r = lane & 31;
+__device__ __forceinline__ void infer_hidden_epilogue(__bf16* act, const float* __restrict__ bias,
+                                                      const f32x16 (&acc)[4][2]) {
+  const int lane = threadIdx.x & 63, r = lane & 31, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int col = 32 * t + r;
+  for (int c = 0; c < 2; ++c) {
+    const int col = 32 * (2 * w + c) + r;
     const float b = bias[col];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int row = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-      my[row * kInferLd + col] = to_bf16(gelu(acc[t][e] + b));
-    }
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = 32 * rt + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        act[row * kInferLd + col] = to_bf16(gelu(acc[rt][c][e] + b));
+      }
   }
 }
 
@@ -292,39 +303,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                       float* __restrict__ y) {
   __shared__ __bf16 act[kInferRows * kInferLd];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t g0 = (int64_t)blockIdx.x * kInferRows + 32 * w;   // global row of the wave's first row
-  __bf16* my = act + 32 * w * kInferLd;
-  {   // scaled inputs in columns 0..15 (zero beyond n_in and beyond n)
-    const int row = lane & 31, j0 = (lane >> 5) * 8;
+  const int64_t g0 = (int64_t)blockIdx.x * kInferRows;   // global row of the block's first row
+  {   // scaled inputs in columns 0..15 (zero beyond n_in and beyond n); wave w fills rows 32w ..
+    const int row = 32 * w + (lane & 31), j0 = (lane >> 5) * 8;
     const int64_t gi = g0 + row;
 #pragma unroll
     for (int j = j0; j < j0 + 8; ++j) {
       float v = 0.0f;
       if (gi < n && j < n_in) v = 2.0f * (x[gi * n_in + j] - lohi[j]) / (lohi[32 + j] - lohi[j]) - 1.0f;
-      my[row * kInferLd + j] = to_bf16(v);
+      act[row * kInferLd + j] = to_bf16(v);
     }
   }
   __syncthreads();
-  f32x16 acc[8];
-  infer_layer<16>(my, W1, 8, acc);
+  f32x16 acc[4][2];
+  infer_layer<16>(act, W1, 8, acc);
   __syncthreads();
-  infer_hidden_epilogue(my, b1, acc);
+  infer_hidden_epilogue(act, b1, acc);
   __syncthreads();
-  infer_layer<kInferW>(my, W2, 8, acc);
+  infer_layer<kInferW>(act, W2, 8, acc);
   __syncthreads();
-  infer_hidden_epilogue(my, b2, acc);
+  infer_hidden_epilogue(act, b2, acc);
   __syncthreads();
-  infer_layer<kInferW>(my, W3, 8, acc);
+  infer_layer<kInferW>(act, W3, 8, acc);
   __syncthreads();
-  infer_hidden_epilogue(my, b3, acc);
+  infer_hidden_epilogue(act, b3, acc);
   __syncthreads();
-  infer_layer<kInferW>(my, W4, 1, acc);   // output layer: rows of W4 padded to 32, column 0 real
-  if ((lane & 31) == 0) {
+  infer_layer<kInferW>(act, W4, 1, acc);   // output layer: rows of W4 padded to 32, column 0 real (wave 0)
+  if (w == 0 && (lane & 31) == 0) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int row = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-      if (g0 + row < n) y[g0 + row] = (acc[0][e] + b4[0]) * y_scale;
-    }
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = 32 * rt + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (g0 + row < n) y[g0 + row] = (acc[rt][0][e] + b4[0]) * y_scale;
+      }
   }
 }
 
