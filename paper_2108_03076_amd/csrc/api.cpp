@@ -827,14 +827,22 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
     const int64_t cost = it->second;
     mode = (cost >= 0 && cost <= 2 * (int64_t)std::max(1, n_slots)) ? PMC_MODE_FUSED : PMC_MODE_TWO_PHASE;
   }
-  // The compiled evaluator of stored paths gives each lane several
-  // consecutive paths (one 16-byte load per slot) when the path count and
-  // the buffer's alignment allow it.
+  // The compiled evaluator of stored paths gives each lane P consecutive
+  // paths (one or more 16-byte loads per slot) when the path count and the
+  // buffer's alignment allow it: 16 bytes' worth always, and up to 64 bytes
+  // while the launch keeps at least one wave per SIMD (2^16 lanes), since the
+  // wave-uniform work per slot is shared by more paths.
   int lanes = 1;
   if (mode == PMC_MODE_TWO_PHASE && o->engine != PMC_ENGINE_INTERPRETER && n_slots > 0) {
-    const int want = sizeof(T) == 8 ? 2 : 4;
-    const bool aligned = !given_paths || ((uintptr_t)given_paths % (want * sizeof(T))) == 0;
-    if (N % (uint64_t)want == 0 && aligned) lanes = want;
+    const int base_p = 16 / (int)sizeof(T);
+    for (int want = 4 * base_p; want >= base_p; want /= 2) {
+      const bool aligned = !given_paths || ((uintptr_t)given_paths % (want * sizeof(T))) == 0;
+      const bool waves = want == base_p || N / (uint64_t)want >= (1u << 16);
+      if (N % (uint64_t)want == 0 && aligned && waves) {
+        lanes = want;
+        break;
+      }
+    }
   }
   const uint64_t tile_paths = (uint64_t)block * (uint64_t)lanes;
   const uint32_t tiles = (uint32_t)((N + tile_paths - 1) / tile_paths);

@@ -16,7 +16,8 @@ hipcc = shutil.which("hipcc")
                                        ("C1", ("double", 0, 1, 0, 1, 0)), ("C3", ("float", 0, 1, 1, 4, 0)),
                                        ("C2", ("float", 1, 3, 1, 4, 0)), ("C1", ("double", 0, 1, 1, 2, 0)),
                                        ("C2", ("float", 1, 3, 0, 1, 16)), ("C1", ("double", 0, 1, 0, 1, 1)),
-                                       ("C2", ("double", 0, 3, 0, 1, 16))])
+                                       ("C2", ("double", 0, 3, 0, 1, 16)), ("C3", ("float", 0, 1, 1, 16, 0)),
+                                       ("C1", ("double", 0, 1, 1, 8, 0))])
 def test_generated_payoff_compiles(tmp_path, name, defs):
     import paper_2108_03076_amd as P
     cfg = W.CONFIGS[name]

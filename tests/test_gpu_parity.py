@@ -211,6 +211,27 @@ def test_c3_full_size_sampled_paths():
         assert r["path_dates"] == n * 1260
 
 
+@pytest.mark.parametrize("name", ["c3", "c1"])
+def test_stored_path_evaluator_at_full_size_equals_fused(name):
+    """At 2^20 paths the stored-path evaluator gives each lane 16 FP32 (or
+    8 FP64) consecutive paths; every per-path payoff equals the fused
+    kernel's bit for bit (the same path values and the same operations)."""
+    import paper_2108_03076_amd as P
+    cfg = W.C3 if name == "c3" else _small(W.C1, n_paths=1 << 20)
+    n = cfg.n_paths
+    print(f"[parity] {name} full size: two-phase against fused", flush=True)
+    pay = gpu_payoff(cfg)
+    dt = torch.float64 if cfg.precision == "f64" else torch.float32
+    outs = {}
+    for mode in ("fused", "two_phase"):
+        out = torch.empty(n, dtype=dt, device="cuda")
+        r = P.price(pay, cfg.tenv, cfg.params, **model_kw(cfg), **opts_kw(cfg, n, mode=mode, payoffs=out))
+        assert r["mode_used"] == (2 if mode == "fused" else 1)
+        outs[mode] = (out, r)
+    assert torch.equal(outs["fused"][0], outs["two_phase"][0])
+    assert outs["fused"][1]["sum"] == pytest.approx(outs["two_phase"][1]["sum"], rel=1e-12)
+
+
 def test_c2_full_size_sampled_paths():
     import paper_2108_03076_amd as P
     cfg = W.C2
