@@ -29,7 +29,7 @@ struct McLaunch {
   int n_work;
   uint32_t* queue;            // work counter (persistent launch) or nullptr
   double2* partial;           // per item: (sum, sum of squares)
-  uint32_t* done;             // per instance: finished-tile counter (zeroed by launch_prep)
+  uint32_t* done;             // batches: per-instance finished-tile counter (zeroed by launch_prep)
   double2* result;            // per instance: (sum, sum of squares); may be mapped host memory
   void* payoff_out;           // optional per-path payoffs of instance 0
   const void* paths;          // stored prices [slot][asset][path] (two-phase)

@@ -150,8 +150,9 @@ struct Args {
   int n_work;
   uint32_t* queue;
   double2* partial;
-  uint32_t* done;        // per instance: finished tiles (zero at launch)
-  double2* result;       // per instance: (sum, sum of squares), written by the last tile's block
+  uint32_t* done;        // batches: per-instance finished tiles (zero at launch)
+  double2* result;       // per instance: (sum, sum of squares); batches: written by the block that
+                         // finishes the instance's last tile (one instrument: by k_finish)
   const double* chol_in; // correlation matrices (A x A per instance)
   int* status;           // per instance: 0, or 1 if the correlation is not positive definite
   int factor;            // 1: each block factors instance 0's matrix itself (single instrument)
