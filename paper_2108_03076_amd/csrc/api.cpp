@@ -660,7 +660,8 @@ int resolve_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec,
   }
   hipFunction_t f = nullptr;
   std::string err;
-  int st = p->jit.get(p->prog, c->device, prec, o->rng, A, mem, &f, err, lanes, full, tenv);
+  const bool single = !L.queue && !L.order;
+  int st = p->jit.get(p->prog, c->device, prec, o->rng, A, mem, &f, err, lanes, full, tenv, single);
   if (st != PMC_OK) return fail(c, st, err);
   if (cap) {
     char kb[64];

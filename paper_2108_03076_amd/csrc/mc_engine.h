@@ -44,14 +44,28 @@ template <> struct Num<float> {
     return fmaf((float)(x >> 9), 0x1p-23f, 0x1p-24f);
   }
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  // f = 1 + (x >> 9) 2^-23; u = f - (1 - 2^-24) is exact (Sterbenz), and
+  // 1 - u and 2u - 1 = u - (1 - u) are multiples of 2^-24 below 1: exact.
+  static __device__ __forceinline__ float word_u(uint32_t x) {
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, x, 9u)) - 0x1.fffffep-1f;
+  }
   static __device__ __forceinline__ float normal_word(uint32_t x) {
-    // f = 1 + (x >> 9) 2^-23; u = f - (1 - 2^-24) is exact (Sterbenz), and
-    // 1 - u and 2u - 1 = u - (1 - u) are multiples of 2^-24 below 1: exact.
-    const float f = __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, x, 9u));
-    const float u = f - 0x1.fffffep-1f;
+    const float u = word_u(x);
+    return (u - (1.0f - u)) * normal_g(u);
+  }
+  // s Phi^-1(u) with the scale taken into 2u - 1: one rounding of (2u - 1) s
+  // (2s is exact), then the same g(w).
+  static __device__ __forceinline__ float normal_word_scaled(uint32_t x, float s) {
+    const float u = word_u(x);
+    return fmaf(u, 2.0f * s, -s) * normal_g(u);
+  }
+  // Log-prices are held in units of log2 (a price is s0 2^x): one
+  // exponential instruction per price.
+  static constexpr float kLog = 1.4426950408889634f;
+  static __device__ __forceinline__ float exps(float x) { return __builtin_amdgcn_exp2f(x); }
+  static __device__ __forceinline__ float normal_g(float u) {
     const float v = 1.0f - u;
     const float t = u * v;
-    const float xs = u - v;
     // d = w - 2.5 = -ln2 (log2 t + 2) - 2.5
     const float d = fmaf(__builtin_amdgcn_logf(t), -0x1.62e430p-1f, -0x1.f17218p+1f);
     float g = 3.9583209598959e-08f;
@@ -77,9 +91,8 @@ template <> struct Num<float> {
       h = fmaf(h, e, 4.107142925262451f);
       g = tail ? h : g;
     }
-    return xs * g;
+    return g;
   }
-  static __device__ __forceinline__ float expv(float x) { return __expf(x); }
   static __device__ __forceinline__ float div(float a, float b) { return a * rcp(b); }
 };
 
@@ -129,7 +142,10 @@ template <> struct Num<double> {
     return q < 0 ? -v : v;
   }
   static __device__ __forceinline__ double normal_word(uint32_t x) { return normal(uniform(x)); }
-  static __device__ __forceinline__ double expv(double x) { return exp(x); }
+  static __device__ __forceinline__ double normal_word_scaled(uint32_t x, double s) { return s * normal_word(x); }
+  // natural log-prices (a price is s0 e^x)
+  static constexpr double kLog = 1.0;
+  static __device__ __forceinline__ double exps(double x) { return exp(x); }
   static __device__ __forceinline__ double div(double a, double b) { return a / b; }
 };
 
@@ -186,32 +202,6 @@ __device__ __forceinline__ InstDesc load_desc(const InstDesc* base, int i) {
 }
 
 // ------------------------------------------------------- path sources -----
-// Per-instance model constants, uniform across the wave.
-template <typename T, int A>
-struct Model {
-  T mu[A], sig[A], s0[A];
-  T L[A][A];
-  // The factor comes from the prepared table, or (own) from the block's own
-  // factorisation, held in scalar registers (lf, row-major).
-  __device__ __forceinline__ void load(const Args<T>& g, const InstDesc& D, const T* lf, bool own) {
-    kptr<T> m = K(g.rtab) + D.model_off;
-#pragma unroll
-    for (int a = 0; a < A; ++a) { mu[a] = m[a]; sig[a] = m[A + a]; s0[a] = m[2 * A + a]; }
-    if (own) {
-#pragma unroll
-      for (int i = 0; i < A; ++i)
-#pragma unroll
-        for (int j = 0; j < A; ++j) L[i][j] = lf[i * A + j];
-    } else {
-      kptr<double> l = K(g.chol) + D.chol_off;
-#pragma unroll
-      for (int i = 0; i < A; ++i)
-#pragma unroll
-        for (int j = 0; j < A; ++j) L[i][j] = (T)l[i * A + j];
-    }
-  }
-};
-
 // A wave-uniform value, marked as such (kept in scalar registers).
 __device__ __forceinline__ float uniform_value(float x) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
@@ -221,6 +211,44 @@ __device__ __forceinline__ double uniform_value(double x) {
   const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll)), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+
+// Per-instance model constants, uniform across the wave.
+template <typename T, int A>
+struct Model {
+  // Per unit time and in the log units of Num<T>: drift dr = kLog (r - sigma^2/2)
+  // and diffusion C = kLog sigma_a L_ak, so a step is
+  // x_a += dr_a dt + sum_k C_ak (sqrt(dt) z_k).
+  T dr[A], s0[A];
+  T C[A][A];
+  // The diffusion factor comes from the prepared FP64 Cholesky table, or
+  // (own) from the block's own coefficients, already scaled and held in
+  // scalar registers (lf: C row-major, then dr).
+  __device__ __forceinline__ void load(const Args<T>& g, const InstDesc& D, const T* lf, bool own) {
+    kptr<T> m = K(g.rtab) + D.model_off;
+#pragma unroll
+    for (int a = 0; a < A; ++a) s0[a] = m[2 * A + a];
+    if (own) {
+#pragma unroll
+      for (int i = 0; i < A; ++i) {
+        dr[i] = lf[A * A + i];
+#pragma unroll
+        for (int j = 0; j < A; ++j) C[i][j] = lf[i * A + j];
+      }
+    } else {
+      kptr<double> l = K(g.chol) + D.chol_off;
+#pragma unroll
+      for (int i = 0; i < A; ++i) {
+        dr[i] = drift_coef(m[i]);
+#pragma unroll
+        for (int j = 0; j < A; ++j) C[i][j] = diffusion_coef(l[i * A + j], m[A + i]);
+      }
+    }
+  }
+  // the same arithmetic wherever the coefficients are made, so that a path
+  // is the same bit for bit whichever kernel generates it
+  static __device__ __forceinline__ T drift_coef(T mu) { return mu * Num<T>::kLog; }
+  static __device__ __forceinline__ T diffusion_coef(double l, T sig) { return ((T)l * sig) * Num<T>::kLog; }
+};
 
 // FP64 Cholesky-Banachiewicz (row by row) of the m x m matrix a into the
 // lower triangle of l (upper part zeroed); false if a is not positive
@@ -470,31 +498,35 @@ struct GenSource {
     }
   }
 
-  // one GBM step from the slot's normals z and step sizes (dt, sqrt dt)
-  __device__ __forceinline__ void advance(const T (&z)[A], T dt, T sdt) {
+  // one GBM step from the slot's words and step sizes (dt, sqrt dt): the
+  // normals come out scaled by sqrt dt, and each log-price takes its drift
+  // and then its correlated terms (every addition on the log-price itself)
+  __device__ __forceinline__ void advance(const uint32_t (&xw)[A], T dt, T sdt) {
+    T zs[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) zs[a] = Num<T>::normal_word_scaled(xw[a], sdt);
 #pragma unroll
     for (int a = 0; a < A; ++a) {
-      T wa = T(0);
+      T xa = x[a] + M.dr[a] * dt;
 #pragma unroll
-      for (int k = 0; k <= a; ++k) wa += M.L[a][k] * z[k];
-      x[a] = x[a] + M.mu[a] * dt + (M.sig[a] * sdt) * wa;
+      for (int k = 0; k <= a; ++k) xa = xa + M.C[a][k] * zs[k];
+      x[a] = xa;
     }
   }
+  __device__ __forceinline__ T price(int a) const { return M.s0[a] * Num<T>::exps(x[a]); }
 
   // one GBM step to slot q (all assets); optionally record words/normals
   template <bool LO = false>
   __device__ __forceinline__ void step(int q, uint32_t* wout, T* zout, uint32_t npath) {
     uint32_t xw[A];
     words<LO>(q, xw);
-    T z[A];
 #pragma unroll
     for (int a = 0; a < A; ++a) {
-      z[a] = Num<T>::normal_word(xw[a]);
       const size_t w = (size_t)(q * A + a);
       if (wout) wout[w * npath + path] = xw[a];
-      if (zout) zout[w * npath + path] = z[a];
+      if (zout) zout[w * npath + path] = Num<T>::normal_word(xw[a]);
     }
-    advance(z, slotc[2 * q], slotc[2 * q + 1]);
+    advance(xw, slotc[2 * q], slotc[2 * q + 1]);
   }
 
   // Generates slots up to s + WS - 1 (from the spot again on a backward
@@ -511,7 +543,7 @@ struct GenSource {
     for (int j = 0; j < cnt; ++j) {
       step(s + j, nullptr, nullptr, 0);
 #pragma unroll
-      for (int a = 0; a < A; ++a) win[(j * A + a) & (kWindow - 1)] = M.s0[a] * Num<T>::expv(x[a]);
+      for (int a = 0; a < A; ++a) win[(j * A + a) & (kWindow - 1)] = price(a);
     }
     next_slot = s + cnt;
     base = s;
@@ -563,12 +595,9 @@ struct GenSource {
 #pragma unroll
         for (int a = 0; a < A; ++a) hw[a] = sobol_hi[nq * A + a];
       }
-      T z[A];
+      advance(xw, cdt, csdt);
 #pragma unroll
-      for (int a = 0; a < A; ++a) z[a] = Num<T>::normal_word(xw[a]);
-      advance(z, cdt, csdt);
-#pragma unroll
-      for (int a = 0; a < A; ++a) win[(q * A + a) & (kWin - 1)] = M.s0[a] * Num<T>::expv(x[a]);
+      for (int a = 0; a < A; ++a) win[(q * A + a) & (kWin - 1)] = price(a);
     }
   }
 
@@ -898,10 +927,19 @@ struct Interp {
 // is then P * blockDim paths.
 // FULL > 0: generated paths are held whole (GenSource's CAP; every
 // instance of the launch has n_slots * A <= FULL).
-template <typename T, int RNG, int A, bool MEM, class Eval, int P = 1, int FULL = 0>
+// SINGLE: the launch prices one instrument in a fixed grid stride (no work
+// queue, no instance order), so the batch machinery is compiled out.
+template <typename T, int RNG, int A, bool MEM, class Eval, int P = 1, int FULL = 0, bool SINGLE = false>
 __device__ __forceinline__ void mc_body(const Args<T>& g) {
   static_assert(P == 1 || MEM, "several paths per lane are for stored paths only");
   static_assert(FULL == 0 || !MEM, "whole-path windows are for generated paths");
+  // Wave priorities: the instruction arbiter favours older waves among equal
+  // priorities, so a block that arrives a little later would have its set-up
+  // (one thread's FP64 factorisation, the Sobol table, the barrier) starved by
+  // older waves' tiles and finish last.  Set-up runs at the top priority and,
+  // in a fixed stride, a wave with more tiles still to do outranks one on its
+  // last, which evens out the waves' finishing times.
+  __builtin_amdgcn_s_setprio(3);
   __shared__ double red[8];
   __shared__ int frames_all[4][3 * kMaxLoopDepth];
   __shared__ int item_s;
@@ -910,11 +948,12 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
   // A single fused instrument: one thread of each block factors the
   // correlation matrix into LDS (block 0 also reports whether it is positive
   // definite) while the others build the Sobol table; after the barrier that
-  // publishes both, every thread keeps the factor in scalar registers.  (The
-  // choice is an explicit flag, never a null test of an LDS pointer: an LDS
-  // array may sit at address 0.)
+  // publishes both, every thread keeps the step coefficients made from the
+  // factor and the instrument's model in scalar registers.  (The choice is
+  // an explicit flag, never a null test of an LDS pointer: an LDS array may
+  // sit at address 0.)
   constexpr int kLA = A > 0 ? A * A : 1;
-  T l_own[kLA] = {};   // the block's factor in working precision (wave-uniform)
+  T l_own[kLA + A] = {};   // the block's C (row-major), then dr: wave-uniform
   const bool own = !MEM && g.factor != 0;
   __shared__ double chol_sh[kLA];
   if (own && threadIdx.x == 0) {
@@ -932,8 +971,14 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
   }
   if (own) {
     if (!has_lo) __syncthreads();
+    kptr<T> m = K(g.rtab) + load_desc(g.desc, 0).model_off;
 #pragma unroll
-    for (int k = 0; k < kLA; ++k) l_own[k] = uniform_value((T)chol_sh[k]);
+    for (int i = 0; i < A; ++i) {
+#pragma unroll
+      for (int j = 0; j < A; ++j)
+        l_own[i * A + j] = uniform_value(Model<T, A>::diffusion_coef(chol_sh[i * A + j], m[A + i]));
+      l_own[kLA + i] = uniform_value(Model<T, A>::drift_coef(m[i]));
+    }
   }
   lwptr<T> mem_win = nullptr;
   if constexpr (MEM && P > 1) {
@@ -944,9 +989,10 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
   // fixed grid stride (single instrument: the grid is at most what fits on
   // the chip, so per-block set-up is paid once per resident block).
   double bs = 0.0, bss = 0.0;   // fixed stride: this thread's sums over its tiles
+  const bool queue = !SINGLE && g.queue != nullptr;
   int item = (int)blockIdx.x - (int)gridDim.x;
   for (;;) {
-    if (g.queue) {
+    if (queue) {
       if (threadIdx.x == 0) item_s = (int)atomicAdd(g.queue, 1u);
       __syncthreads();
       item = item_s;
@@ -955,9 +1001,11 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
       item += (int)gridDim.x;
     }
     if (item >= g.n_work) break;
+    if (queue || item + (int)gridDim.x < g.n_work) __builtin_amdgcn_s_setprio(2);
+    else __builtin_amdgcn_s_setprio(1);
     // item -> (instance, tile): consecutive items cover one instance's tiles
     int2 wi = make_int2(0, item);
-    if (g.order) wi = make_int2(K(g.order)[item / g.tiles], item % g.tiles);
+    if (!SINGLE && g.order) wi = make_int2(K(g.order)[item / g.tiles], item % g.tiles);
     const InstDesc D = load_desc(g.desc, wi.x);
     double s = 0.0, ss = 0.0;
     for (int r = 0; r < g.ppt; ++r) {
@@ -988,7 +1036,7 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
         }
       }
     }
-    if (!g.queue) {          // one instrument: per-thread sums over its tiles, reduced once below
+    if (!queue) {            // one instrument: per-thread sums over its tiles, reduced once below
       bs += s; bss += ss;
       continue;
     }
@@ -1019,7 +1067,7 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
       }
     }
   }
-  if (!g.queue) {
+  if (!queue) {
     // One block reduction and one partial per block; the finishing kernel
     // that follows on the stream sums the partials in block order.  (A
     // completion counter instead would serialize: device-scope atomics on
@@ -1050,7 +1098,7 @@ __device__ __forceinline__ void pathgen_body(const Args<T>& g, T* out, uint32_t*
     src.step(q, wout, zout, n_paths);
 #pragma unroll
     for (int a = 0; a < A; ++a)
-      out[((size_t)q * A + a) * n_paths + path] = src.M.s0[a] * Num<T>::expv(src.x[a]);
+      out[((size_t)q * A + a) * n_paths + path] = src.price(a);
   }
 }
 

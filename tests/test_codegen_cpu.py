@@ -37,9 +37,10 @@ def test_generated_payoff_compiles(tmp_path, name, defs):
 @pytest.mark.skipif(hipcc is None, reason="hipcc not available")
 def test_whole_path_headline_kernel_fits_eight_waves(tmp_path):
     """The worst-of autocall generated for its template environment, with its
-    path held whole (5 dates x 3 assets in a 16-entry window), compiles at
-    eight waves per SIMD without scratch memory, and its code (the generation
-    exists once) stays far below the 64 KB instruction cache."""
+    path held whole (5 dates x 3 assets in a 16-entry window) and priced as
+    one instrument (no batch queue), compiles at eight waves per SIMD without
+    scratch memory, and its code (the generation exists once) stays far below
+    the 64 KB instruction cache."""
     import re
     import paper_2108_03076_amd as P
     cfg = W.CONFIGS["C2"]
@@ -50,7 +51,7 @@ def test_whole_path_headline_kernel_fits_eight_waves(tmp_path):
     cmd = [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
            "-packed-fp32-ops", "-include", "hip/hip_runtime.h", "--cuda-device-only", "-S", str(f), "-o", str(out),
            "-DPMC_REAL=float", "-DPMC_RNG=1", "-DPMC_A=3", "-DPMC_MEM=0", "-DPMC_P=1", "-DPMC_FULL=16",
-           "-DPMC_WAVES=8"]
+           "-DPMC_WAVES=8", "-DPMC_SINGLE=1"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     asm = out.read_text()
