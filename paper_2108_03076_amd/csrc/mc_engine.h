@@ -221,8 +221,8 @@ struct Model {
   T dr[A], s0[A];
   T C[A][A];
   // The diffusion factor comes from the prepared FP64 Cholesky table, or
-  // (own) from the block's own coefficients, already scaled and held in
-  // scalar registers (lf: C row-major, then dr).
+  // (own) from the block's own coefficients, already made (lf: C row-major,
+  // then dr).
   __device__ __forceinline__ void load(const Args<T>& g, const InstDesc& D, const T* lf, bool own) {
     kptr<T> m = K(g.rtab) + D.model_off;
 #pragma unroll
@@ -946,21 +946,29 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
   __shared__ int last_s;
   int* frames = frames_all[threadIdx.x >> 6];
   // A single fused instrument: one thread of each block factors the
-  // correlation matrix into LDS (block 0 also reports whether it is positive
-  // definite) while the others build the Sobol table; after the barrier that
-  // publishes both, every thread keeps the step coefficients made from the
-  // factor and the instrument's model in scalar registers.  (The choice is
-  // an explicit flag, never a null test of an LDS pointer: an LDS array may
-  // sit at address 0.)
+  // correlation matrix and makes the step coefficients from the factor and
+  // the instrument's model into LDS (block 0 also reports whether the matrix
+  // is positive definite) while the others build the Sobol table; after the
+  // barrier that publishes both, every thread keeps the coefficients in
+  // registers.  (The choice is an explicit flag, never a null test of an LDS
+  // pointer: an LDS array may sit at address 0.)
   constexpr int kLA = A > 0 ? A * A : 1;
   T l_own[kLA + A] = {};   // the block's C (row-major), then dr: wave-uniform
   const bool own = !MEM && g.factor != 0;
   __shared__ double chol_sh[kLA];
+  __shared__ T coef_sh[kLA + A];
   if (own && threadIdx.x == 0) {
     const bool ok = chol_factor(K(g.chol_in), chol_sh, A);
     // (host-mapped memory, read after the host's wait on the launch's end
     // event, whose system-scope release publishes it)
     if (blockIdx.x == 0) g.status[0] = ok ? 0 : 1;
+    kptr<T> m = K(g.rtab) + load_desc(g.desc, 0).model_off;
+#pragma unroll
+    for (int i = 0; i < A; ++i) {
+#pragma unroll
+      for (int j = 0; j < A; ++j) coef_sh[i * A + j] = Model<T, A>::diffusion_coef(chol_sh[i * A + j], m[A + i]);
+      coef_sh[kLA + i] = Model<T, A>::drift_coef(m[i]);
+    }
   }
   bool has_lo = false;
   lptr<uint32_t> lo_tab = nullptr;
@@ -971,14 +979,8 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
   }
   if (own) {
     if (!has_lo) __syncthreads();
-    kptr<T> m = K(g.rtab) + load_desc(g.desc, 0).model_off;
 #pragma unroll
-    for (int i = 0; i < A; ++i) {
-#pragma unroll
-      for (int j = 0; j < A; ++j)
-        l_own[i * A + j] = uniform_value(Model<T, A>::diffusion_coef(chol_sh[i * A + j], m[A + i]));
-      l_own[kLA + i] = uniform_value(Model<T, A>::drift_coef(m[i]));
-    }
+    for (int k = 0; k < kLA + A; ++k) l_own[k] = coef_sh[k];
   }
   lwptr<T> mem_win = nullptr;
   if constexpr (MEM && P > 1) {
