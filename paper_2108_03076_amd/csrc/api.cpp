@@ -661,7 +661,8 @@ int resolve_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec,
   hipFunction_t f = nullptr;
   std::string err;
   const bool single = !L.queue && !L.order;
-  int st = p->jit.get(p->prog, c->device, prec, o->rng, A, mem, &f, err, lanes, full, tenv, single);
+  const bool own = !mem && L.factor != 0;
+  int st = p->jit.get(p->prog, c->device, prec, o->rng, A, mem, &f, err, lanes, full, tenv, single, own);
   if (st != PMC_OK) return fail(c, st, err);
   if (cap) {
     char kb[64];

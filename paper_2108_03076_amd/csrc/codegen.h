@@ -31,7 +31,7 @@ constexpr int64_t kMaxUnrolled = 4000;
 
 // Compiled kernels of one payoff, keyed by (device, precision, rng, assets,
 // memory source, paths per lane, whole-path capacity, single instrument,
-// template environment).  Owned by the payoff object.
+// own factorisation, template environment).  Owned by the payoff object.
 class JitCache {
  public:
   ~JitCache();
@@ -41,16 +41,18 @@ class JitCache {
   // the one template environment every instance of the launch has, for a
   // kernel generated for it; null for the generic kernel.  single: the
   // launch prices one instrument without a work queue or instance order,
-  // and the kernel leaves out the batch machinery.
+  // and the kernel leaves out the batch machinery.  own: every launch has
+  // each block factor the correlation matrix itself (Args::factor = 1), and
+  // the kernel leaves out the prepared-factor branch.
   int get(const Program& P, int device, int precision, int rng, int n_assets, bool from_memory,
           hipFunction_t* out, std::string& err, int lanes = 1, int full = 0, const int32_t* tenv = nullptr,
-          bool single = false);
+          bool single = false, bool own = false);
 
  private:
   // hipRTC compile and module load of one variant; waves > 0 asks for that
   // many waves per SIMD.
   int compile(const std::string& src, int precision, int rng, int n_assets, bool mem, int lanes, int full,
-              bool single, int waves, hipModule_t* mod, hipFunction_t* fn, std::string& err);
+              bool single, bool own, int waves, hipModule_t* mod, hipFunction_t* fn, std::string& err);
   std::mutex mu_;
   std::map<std::string, std::pair<hipModule_t, hipFunction_t>> k_;
   std::string src_;  // generic generated payoff source (built once)

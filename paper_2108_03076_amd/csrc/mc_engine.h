@@ -64,8 +64,9 @@ template <> struct Num<float> {
   static constexpr float kLog = 1.4426950408889634f;
   static __device__ __forceinline__ float exps(float x) { return __builtin_amdgcn_exp2f(x); }
   static __device__ __forceinline__ float normal_g(float u) {
-    const float v = 1.0f - u;
-    const float t = u * v;
+    // t = u (1 - u) rounded once: 1 - u is exact, so this is the same value
+    // as the product u * (1 - u), in one instruction
+    const float t = fmaf(-u, u, u);
     // d = w - 2.5 = -ln2 (log2 t + 2) - 2.5
     const float d = fmaf(__builtin_amdgcn_logf(t), -0x1.62e430p-1f, -0x1.f17218p+1f);
     float g = 3.9583209598959e-08f;
@@ -929,7 +930,10 @@ struct Interp {
 // instance of the launch has n_slots * A <= FULL).
 // SINGLE: the launch prices one instrument in a fixed grid stride (no work
 // queue, no instance order), so the batch machinery is compiled out.
-template <typename T, int RNG, int A, bool MEM, class Eval, int P = 1, int FULL = 0, bool SINGLE = false>
+// OWN: every launch of the kernel has each block factor its instrument's
+// matrix (Args::factor is 1), so the prepared-factor branch is compiled out.
+template <typename T, int RNG, int A, bool MEM, class Eval, int P = 1, int FULL = 0, bool SINGLE = false,
+          bool OWN = false>
 __device__ __forceinline__ void mc_body(const Args<T>& g) {
   static_assert(P == 1 || MEM, "several paths per lane are for stored paths only");
   static_assert(FULL == 0 || !MEM, "whole-path windows are for generated paths");
@@ -954,7 +958,8 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
   // pointer: an LDS array may sit at address 0.)
   constexpr int kLA = A > 0 ? A * A : 1;
   T l_own[kLA + A] = {};   // the block's C (row-major), then dr: wave-uniform
-  const bool own = !MEM && g.factor != 0;
+  static_assert(!OWN || !MEM, "stored paths use the prepared factor");
+  const bool own = OWN || (!MEM && g.factor != 0);
   __shared__ double chol_sh[kLA];
   __shared__ T coef_sh[kLA + A];
   if (own && threadIdx.x == 0) {

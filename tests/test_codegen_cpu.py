@@ -17,7 +17,13 @@ hipcc = shutil.which("hipcc")
                                        ("C2", ("float", 1, 3, 1, 4, 0)), ("C1", ("double", 0, 1, 1, 2, 0)),
                                        ("C2", ("float", 1, 3, 0, 1, 16)), ("C1", ("double", 0, 1, 0, 1, 1)),
                                        ("C2", ("double", 0, 3, 0, 1, 16)), ("C3", ("float", 0, 1, 1, 16, 0)),
-                                       ("C1", ("double", 0, 1, 1, 8, 0))])
+                                       ("C1", ("double", 0, 1, 1, 8, 0)),
+                                       # one instrument, each block factoring its own matrix
+                                       ("C2", ("float", 1, 3, 0, 1, 16, 1, 1)),
+                                       ("C1", ("double", 0, 1, 0, 1, 1, 1, 1)),
+                                       ("C3", ("float", 0, 1, 0, 1, 0, 1, 1)),
+                                       # one instrument from stored paths (prepared factor)
+                                       ("C3", ("float", 0, 1, 1, 16, 0, 1, 0))])
 def test_generated_payoff_compiles(tmp_path, name, defs):
     import paper_2108_03076_amd as P
     cfg = W.CONFIGS[name]
@@ -26,10 +32,11 @@ def test_generated_payoff_compiles(tmp_path, name, defs):
     assert "struct GenPayoff" in src and "pmc_jit_mc" in src
     f = tmp_path / "payoff.hip"
     f.write_text(src)
-    real, rng, a, mem, lanes, full = defs
+    real, rng, a, mem, lanes, full, single, own = (defs + (0, 0))[:8]
     cmd = [hipcc, "--offload-arch=gfx950", "-O1", "-std=c++17", "-include", "hip/hip_runtime.h", "-c", str(f),
            "-o", str(tmp_path / "payoff.o"), f"-DPMC_REAL={real}", f"-DPMC_RNG={rng}", f"-DPMC_A={a}",
-           f"-DPMC_MEM={mem}", f"-DPMC_P={lanes}", f"-DPMC_FULL={full}"]
+           f"-DPMC_MEM={mem}", f"-DPMC_P={lanes}", f"-DPMC_FULL={full}", f"-DPMC_SINGLE={single}",
+           f"-DPMC_OWN={own}"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
 
@@ -38,9 +45,10 @@ def test_generated_payoff_compiles(tmp_path, name, defs):
 def test_whole_path_headline_kernel_fits_eight_waves(tmp_path):
     """The worst-of autocall generated for its template environment, with its
     path held whole (5 dates x 3 assets in a 16-entry window) and priced as
-    one instrument (no batch queue), compiles at eight waves per SIMD without
-    scratch memory, and its code (the generation exists once) stays far below
-    the 64 KB instruction cache."""
+    one instrument (no batch queue, each block factoring its own matrix),
+    compiles at eight waves per SIMD without scratch memory, and its code
+    (the generation exists once) stays far below the 64 KB instruction
+    cache."""
     import re
     import paper_2108_03076_amd as P
     cfg = W.CONFIGS["C2"]
@@ -51,7 +59,7 @@ def test_whole_path_headline_kernel_fits_eight_waves(tmp_path):
     cmd = [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
            "-packed-fp32-ops", "-include", "hip/hip_runtime.h", "--cuda-device-only", "-S", str(f), "-o", str(out),
            "-DPMC_REAL=float", "-DPMC_RNG=1", "-DPMC_A=3", "-DPMC_MEM=0", "-DPMC_P=1", "-DPMC_FULL=16",
-           "-DPMC_WAVES=8", "-DPMC_SINGLE=1"]
+           "-DPMC_WAVES=8", "-DPMC_SINGLE=1", "-DPMC_OWN=1"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     asm = out.read_text()
