@@ -627,6 +627,18 @@ int finish(pmc_ctx* c, int n_inst, const uint64_t* n_paths, const int* n_slots, 
 // counts as short.
 constexpr int64_t kShortItem = 64;
 
+// A fixed-stride grid for `items` work items on at most `cap` resident
+// blocks: the fewest blocks that still take ceil(items / cap) items each, so
+// that every block strides over the same number of items (a grid of cap
+// blocks would leave some with one item fewer, and the kernel waits for the
+// blocks with the most).
+int balanced_grid(int items, int cap) {
+  cap = std::max(1, cap);
+  if (items <= cap) return std::max(1, items);
+  const int per = (items + cap - 1) / cap;
+  return (items + per - 1) / per;
+}
+
 // Chooses the Monte Carlo kernel for the requested payoff engine and its
 // grid.  lanes: paths per lane (compiled engine with stored paths only);
 // full, tenv: whole-path capacity and the template environment a compiled
@@ -653,7 +665,7 @@ int resolve_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec,
                               std::to_string(block);
       auto it = c->occupancy.find(key);
       if (it == c->occupancy.end()) it = c->occupancy.emplace(key, mc_occupancy(prec, o->rng, A, p->prog.n_regs, block)).first;
-      grid = std::max(1, std::min(grid, c->n_cu * it->second));
+      grid = balanced_grid(grid, c->n_cu * it->second);
     }
     e.grid = grid;
     return PMC_OK;
@@ -670,7 +682,7 @@ int resolve_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec,
     const std::string key = kb;
     auto it = c->occupancy.find(key);
     if (it == c->occupancy.end()) it = c->occupancy.emplace(key, mc_occupancy_jit(f, block)).first;
-    grid = std::max(1, std::min(grid, c->n_cu * it->second));
+    grid = balanced_grid(grid, c->n_cu * it->second);
   }
   e.jit = true;
   e.f = f;
