@@ -211,13 +211,20 @@ def test_c3_full_size_sampled_paths():
         assert r["path_dates"] == n * 1260
 
 
-@pytest.mark.parametrize("name", ["c3", "c1"])
+FULL_SIZE = {"c3": W.C3, "c1": _small(W.C1, n_paths=1 << 20),
+             # three correlated assets: the fused kernel's blocks make the step
+             # coefficients from their own factorisation, the path generator
+             # from the prepared factor; the paths must still agree bit for bit
+             "c2": W.C2, "c2_f64": _small(W.C2, precision="f64")}
+
+
+@pytest.mark.parametrize("name", list(FULL_SIZE))
 def test_stored_path_evaluator_at_full_size_equals_fused(name):
     """At 2^20 paths the stored-path evaluator gives each lane 16 FP32 (or
     8 FP64) consecutive paths; every per-path payoff equals the fused
     kernel's bit for bit (the same path values and the same operations)."""
     import paper_2108_03076_amd as P
-    cfg = W.C3 if name == "c3" else _small(W.C1, n_paths=1 << 20)
+    cfg = FULL_SIZE[name]
     n = cfg.n_paths
     print(f"[parity] {name} full size: two-phase against fused", flush=True)
     pay = gpu_payoff(cfg)
