@@ -123,7 +123,10 @@ int pmc_payoff_cut(pmc_ctx* ctx, const pmc_payoff* in, pmc_payoff** out);
  * kernel body plus the payoff expression translated to a HIP device function
  * (Sec. 6's code-generation route; compile with -DPMC_REAL=float|double
  * -DPMC_RNG=0|1 -DPMC_A=<assets> -DPMC_MEM=0|1, optionally -DPMC_P=<paths
- * per lane> -DPMC_FULL=<whole-path capacity> -DPMC_WAVES=<waves per SIMD>).
+ * per lane> -DPMC_FULL=<whole-path capacity> -DPMC_WAVES=<waves per SIMD>
+ * -DPMC_SINGLE=1 (one instrument, fixed grid stride: no work queue or
+ * instance order) -DPMC_OWN=1 (each block factors the correlation matrix
+ * itself; generated paths only)).
  * tenv: NULL for the generic function (template values read per instance),
  * else the function generated for that template environment, as the engine
  * builds it for launches whose paths it holds whole (loopif iterations
