@@ -282,6 +282,31 @@ def test_batch_matches_single_and_oracle(engine):
         assert res[i]["n_slots"] == T[i]
 
 
+def test_three_asset_batch_matches_single_fused():
+    """A batch of worst-of autocalls sharing one template environment runs the
+    whole-path kernel with step coefficients made per tile from the prepared
+    factors; a single fused price makes them in each block from its own
+    factorisation.  The paths are the same, so the prices agree up to the
+    order of summation."""
+    import paper_2108_03076_amd as P
+    cfg = W.C2
+    m, n = 4, 4096
+    rng = np.random.default_rng(3)
+    spot = 100.0 * (1.0 + 0.1 * rng.standard_normal((m, 3)))
+    vol = rng.uniform(0.1, 0.4, (m, 3))
+    corr = np.stack([np.array(W.corr_equi(3, r)) for r in rng.uniform(0.0, 0.8, m)])
+    tenv = np.full((m, 1), cfg.tenv[0], np.int32)
+    print("[parity] three-asset batch against single fused", flush=True)
+    pay = gpu_payoff(cfg)
+    res = P.price_batch(pay, tenv, np.zeros((m, 0)), spot=spot, vol=vol, corr=corr, rate=cfg.rate,
+                        years_per_day=cfg.years_per_day, per_instance_model=True, **opts_kw(cfg, n))
+    for i in range(m):
+        one = P.price(pay, cfg.tenv, [], spot=spot[i], vol=vol[i], corr=corr[i], rate=cfg.rate,
+                      years_per_day=cfg.years_per_day, **opts_kw(cfg, n, instance=i, mode="fused"))
+        assert one["mode_used"] == 2
+        assert res[i]["price"] == pytest.approx(one["price"], rel=1e-12, abs=1e-12), (i, res[i], one)
+
+
 def test_batch_per_instance_model_and_determinism():
     import paper_2108_03076_amd as P
     from oracle.mc import estimate
