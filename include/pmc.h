@@ -248,7 +248,7 @@ int pmc_autotune_batch(pmc_ctx* ctx, const pmc_payoff* p, const pmc_batch* batch
                        int* block_out, int* ppt_out);
 
 /* Bump-and-revalue risk over a batch (the risk runs of thousands of
- * pricings of one compiled contract that motivate the engine, Sec. 7).
+ * pricings of one compiled contract that motivate the engine, end of Sec. 6.2).
  * For every instance of the batch (same layout and model rules as
  * pmc_price_batch) the library prices 1 + 4A scenarios: the base model, then
  * for each asset a the spots S_a + h_a and S_a - h_a (h_a = rel_spot_bump *

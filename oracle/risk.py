@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY -- see the package docstring.
 
 The paper motivates pricing one compiled contract many times over: risk
-runs are thousands of pricings of the same instrument (Sec. 7).  The Greeks
+runs are thousands of pricings of the same instrument (end of Sec. 6.2).  The Greeks
 of one instrument are central differences of Monte Carlo prices under bumped
 models, every scenario driven by the same random words (the same instance
 counter and seed, hence the same normals):

@@ -72,7 +72,7 @@ struct Pack {
 
 struct GraphCache {
   hipGraphExec_t exec = nullptr;
-  std::string key;
+  std::vector<uint8_t> key;
   ~GraphCache() { if (exec) (void)hipGraphExecDestroy(exec); }
 };
 
@@ -257,8 +257,8 @@ extern "C" int pmc_payoff_source(const pmc_payoff* p, const int32_t* tenv, char*
     std::string err;
     const int st = pmc::plan(p->prog, tenv, g, err);
     if (st != PMC_OK) return st;
-    gp = &g;
     fixed = pmc::unrolled_size(p->prog, g, p->prog.root, pmc::kMaxUnrolled + 1) <= pmc::kMaxUnrolled;
+    if (fixed) gp = &g;   // else the generic function serves this environment too
   }
   const std::string s = std::string(pmc::kEngineSource) + "\n" + generate_payoff(p->prog, gp, fixed);
   *len = s.size();
@@ -1088,17 +1088,33 @@ int batch_enqueue(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, const Batc
   return launch_engine(c, p, o, prec, false, bp.L, bp.grid, bp.block, 1, 0, bp.full, spec_tenv(bp));
 }
 
+// Everything a captured batch graph bakes in: the kernel variant, the grid,
+// and every launch argument (pointers and values alike: the Philox key, the
+// Sobol shape, tile counts).  A replay is valid only for an identical key.
+void batch_graph_key(std::vector<uint8_t>& k, const pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp,
+                     const pmc_opts* o, int prec) {
+  const McLaunch& L = bp.L;
+  k.clear();
+  put(k, p->serial);   // never reused: a freed payoff's kernels are never replayed
+  put(k, prec); put(k, o->rng); put(k, o->engine);
+  put(k, bp.n_inst); put(k, bp.grid); put(k, bp.block); put(k, bp.ppt); put(k, bp.full); put(k, bp.spec);
+  put(k, bp.tenv.size());
+  if (!bp.tenv.empty()) put_bytes(k, bp.tenv.data(), bp.tenv.size() * sizeof(int32_t));
+  put(k, L.code); put(k, L.consts); put(k, L.desc); put(k, L.itab); put(k, L.rtab); put(k, L.chol);
+  put(k, L.chol_in); put(k, L.status); put(k, L.factor); put(k, L.sobol); put(k, L.sobol_bits);
+  put(k, L.sobol_hi); put(k, L.sobol_dims); put(k, L.order); put(k, L.tiles); put(k, L.n_work);
+  put(k, L.queue); put(k, L.partial); put(k, L.done); put(k, L.result); put(k, L.payoff_out);
+  put(k, L.paths); put(k, L.k0); put(k, L.k1); put(k, L.ppt); put(k, L.n_assets); put(k, L.n_regs);
+  // buffers the preparation kernel writes
+  put(k, c->chol.p); put(k, c->results.dev); put(k, c->counters.p);
+}
+
 int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_opts* o, float* ms_out) {
   const int prec = o->precision == PMC_FP64 ? 1 : 0;
   const int A = (int)p->prog.assets.size();
-  std::ostringstream key;
-  key << p->hash << ':' << bp.n_inst << ':' << bp.grid << ':' << bp.block << ':' << bp.ppt << ':' << bp.L.n_work
-      << ':' << prec << ':' << o->rng << ':' << o->engine << ':' << bp.full << ':' << c->blob.p << ':' << c->partial.p << ':' << c->results.dev << ':' << c->counters.p << ':'
-      << c->chol.p << ':' << c->sobol.p << ':' << (const void*)bp.L.sobol_hi << ':' << (const void*)bp.L.desc << ':'
-      << (const void*)bp.L.order;
-  key << ':' << bp.spec;
-  for (int32_t v : bp.tenv) key << ' ' << v;   // the kernel variant
-  if (c->graph.key != key.str()) {
+  std::vector<uint8_t> key;
+  batch_graph_key(key, c, p, bp, o, prec);
+  if (c->graph.key != key) {
     if (c->graph.exec) { (void)hipGraphExecDestroy(c->graph.exec); c->graph.exec = nullptr; }
     c->graph.key.clear();
     hipStream_t cap = c->stream;
@@ -1126,7 +1142,7 @@ int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_op
     (void)hipGraphDestroy(graph);
     if (own) (void)hipStreamDestroy(cap);
     if (e != hipSuccess) return fail(c, PMC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
-    c->graph.key = key.str();
+    c->graph.key = key;
   }
   HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
   HIP_TRY(c, hipGraphLaunch(c->graph.exec, c->stream));
@@ -1135,6 +1151,10 @@ int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_op
   HIP_TRY(c, hipEventElapsedTime(ms_out, c->ev0, c->ev1));
   return PMC_OK;
 }
+
+// A batch tile the kernels can run: whole waves, at most the 256 threads the
+// kernels are compiled for, and 1 .. 1024 paths per thread.
+bool valid_tile(int block, int ppt) { return block >= 64 && block <= 256 && block % 64 == 0 && ppt >= 1 && ppt <= 1024; }
 
 std::string tune_key(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc_opts* o) {
   std::ostringstream k;
@@ -1199,7 +1219,7 @@ extern "C" int pmc_autotune_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_bat
     std::string k;
     int bl, pp;
     while (f >> k >> bl >> pp)
-      if (k == key) {
+      if (k == key && valid_tile(bl, pp)) {   // an entry that is not a launchable tile is ignored
         c->tuned[key] = {bl, pp};
         if (block_out) *block_out = bl;
         if (ppt_out) *ppt_out = pp;

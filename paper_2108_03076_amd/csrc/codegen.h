@@ -47,8 +47,12 @@ class JitCache {
   int get(const Program& P, int device, int precision, int rng, int n_assets, bool from_memory,
           hipFunction_t* out, std::string& err, int lanes = 1, int full = 0, const int32_t* tenv = nullptr,
           bool single = false, bool own = false);
-
  private:
+  // The cache key of a variant; g and spec receive the grid and whether the
+  // kernel is generated for that one template environment.
+  static std::string variant_key(const Program& P, int device, int precision, int rng, int n_assets, bool mem,
+                                 int lanes, int full, const int32_t* tenv, bool single, bool own, Grid& g,
+                                 bool& spec);
   // hipRTC compile and module load of one variant; waves > 0 asks for that
   // many waves per SIMD.
   int compile(const std::string& src, int precision, int rng, int n_assets, bool mem, int lanes, int full,

@@ -1016,8 +1016,10 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
     const InstDesc D = load_desc(g.desc, wi.x);
     double s = 0.0, ss = 0.0;
     for (int r = 0; r < g.ppt; ++r) {
-      const uint32_t path0 = (((uint32_t)wi.y * (uint32_t)g.ppt + (uint32_t)r) * blockDim.x + threadIdx.x) * P;
-      const uint32_t p = path0 < D.n_paths ? path0 : D.n_paths - P;
+      // 64-bit: with n_paths close to 2^32 the last tile's lanes would wrap
+      const uint64_t path0 =
+          (((uint64_t)(uint32_t)wi.y * (uint32_t)g.ppt + (uint32_t)r) * blockDim.x + threadIdx.x) * P;
+      const uint32_t p = path0 < D.n_paths ? (uint32_t)path0 : D.n_paths - P;
       VecT<T, P> v;
       if constexpr (MEM && P > 1) {
         MemSourceLds<T, A, P> src;
@@ -1034,7 +1036,7 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
       }
 #pragma unroll
       for (int e = 0; e < P; ++e) {
-        const uint32_t path = path0 + (uint32_t)e;
+        const uint64_t path = path0 + (uint32_t)e;
         if (path < D.n_paths) {
           const T ve = lane_elem(v, e);
           const double x = (double)ve;
@@ -1096,8 +1098,9 @@ __device__ __forceinline__ void pathgen_body(const Args<T>& g, T* out, uint32_t*
     has_lo = sobol_lo_table(g, sob_lo);
     lo_tab = (lptr<uint32_t>)sob_lo;
   }
-  const uint32_t path = blockIdx.x * blockDim.x + threadIdx.x;
-  if (path >= n_paths) return;
+  const uint64_t gpath = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gpath >= n_paths) return;
+  const uint32_t path = (uint32_t)gpath;
   const InstDesc D = load_desc(g.desc, 0);
   GenSource<T, RNG, A> src;
   src.init(g, D, path, lo_tab, has_lo);

@@ -84,3 +84,5 @@ def test_source_for_a_template_environment():
     c3 = W.CONFIGS["C3"]
     pay3 = P.load_payoff(c3.il, c3.asset_labels, c3.param_labels, c3.tvars)
     assert "read_obs(" in pay3.source(c3.tenv).split("struct GenPayoff")[1]
+    # too long to write out: the generic function serves that environment
+    assert pay3.source(c3.tenv) == pay3.source()
