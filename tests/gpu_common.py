@@ -59,3 +59,43 @@ def sample_ids(n, k, seed=0):
     g = np.random.default_rng(seed)
     ids = np.unique(np.concatenate([[0, 1, n - 1], g.integers(0, n, size=k)]))
     return ids.astype(np.int64)
+
+
+_GOLDEN = None
+
+
+def golden():
+    """Stored oracle values (tests/golden/oracle_values.json, written by
+    tests/golden/make_oracle_values.py from the oracle alone)."""
+    global _GOLDEN
+    if _GOLDEN is None:
+        import json
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_values.json")
+        with open(path) as f:
+            _GOLDEN = json.load(f)
+    return _GOLDEN
+
+
+def band_cap(case, n, tail=1e-6):
+    """(expected, cap) tie-band counts for n paths of a stored case.  The
+    rate is the band count k of M independent oracle paths, taken at its
+    upper bound (k + 3 sqrt(k) + 3) / M; the cap is the count a Poisson
+    variable of that mean exceeds with probability below `tail`."""
+    from scipy.stats import poisson
+    r = golden()["band_rates"][case]
+    k, m = r["band"], r["sample"]
+    lam = n * (k + 3.0 * np.sqrt(k) + 3.0) / m
+    return n * k / m, int(poisson.isf(tail, lam))
+
+
+def check_band(case, band, n=None):
+    """Prints the tie-band count of a per-path comparison and asserts that it
+    is within the cap derived from the case's stored band rate (a band far
+    above its expected size would make the comparison vacuous)."""
+    n = band.size if n is None else n
+    count = int(np.sum(band))
+    exp, cap = band_cap(case, n)
+    print(f"[tie-band] {case}: {count} of {n} paths (expected {exp:.2f}, cap {cap})", flush=True)
+    assert count <= cap, (case, count, exp, cap)
+    return count

@@ -1,0 +1,192 @@
+"""The batched launch (templated instances in one persistent, graph-replayed
+kernel, Sec. 2 and Sec. 6.2) at the shape the benchmark times: the
+1024-instance down-and-out workload with 252..1260 daily dates.
+
+* Sample instances at 2^12 paths, at the tiles (threads per block x paths
+  per thread) 256 x 4 and 128 x 2 forced through the autotuner's cache
+  file, and at the autotuner's own choice: prices against the stored FP64
+  oracle prices on the same streams.
+* Exact pins: a vanishing barrier gives the vanilla call on the same
+  stream; a barrier at or above the spot knocks out on day 0 (price 0).
+* The full batch (1024 x 2^16 paths) at the tuned tile: six instances
+  against the stored full-size oracle prices, and properties that hold at
+  any size (the down-and-out never exceeds the vanilla on the same paths;
+  the vanilla is within its error of Black-Scholes).
+* Graph replays follow every launch argument (the seed, the Sobol shape).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from cases import C4_SAMPLE_PATHS, small
+from gpu_common import golden, gpu_payoff, model_kw, opts_kw
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CFG = W.C4
+
+
+def _sample():
+    g = golden()["c4_sample"]
+    assert g["paths"] == C4_SAMPLE_PATHS
+    inst = g["instances"]
+    ids = np.array([e["id"] for e in inst], dtype=np.uint32)
+    T = np.array([e["T"] for e in inst], dtype=np.int32).reshape(-1, 1)
+    KB = np.array([[e["K"], e["B"]] for e in inst])
+    return inst, ids, T, KB
+
+
+def _tune_key(cache):
+    lines = [l.split() for l in cache.read_text().splitlines() if l.strip()]
+    assert len(lines) == 1 and len(lines[0]) == 3, lines
+    return lines[0][0], int(lines[0][1]), int(lines[0][2])
+
+
+def _check_vs_oracle(res, inst, tag):
+    """Each price within R18's 0.1 standard errors of the oracle's on the
+    same stream; prints the worst case in SE units."""
+    worst = 0.0
+    for r, e in zip(res, inst):
+        d = (r["price"] - e["price"]) / e["se"]
+        worst = max(worst, abs(d))
+        assert abs(r["price"] - e["price"]) <= 0.1 * e["se"], (tag, e["id"], e["T"], r["price"], e["price"], e["se"])
+        assert r["n_slots"] == e["T"] and r["path_dates"] == C4_SAMPLE_PATHS * e["T"]
+    print(f"[batch] {tag}: {len(res)} instances, worst |gpu - oracle| = {worst:.4f} SE", flush=True)
+
+
+def test_sample_instances_at_forced_and_tuned_tiles(tmp_path):
+    import paper_2108_03076_amd as P
+    inst, ids, T, KB = _sample()
+    n = C4_SAMPLE_PATHS
+    pay = gpu_payoff(CFG)
+    kw = dict(**model_kw(CFG), **opts_kw(CFG, n), instance_ids=ids)
+    cache = tmp_path / "tune.txt"
+    print("[batch] autotune with a cache file", flush=True)
+    bl, pp = P.autotune_batch(pay, T, KB, cache_path=str(cache), **kw)
+    key, fbl, fpp = _tune_key(cache)
+    assert (fbl, fpp) == (bl, pp) and bl in (64, 128, 256) and pp in (1, 2, 4)
+    tuned = P.price_batch(pay, T, KB, **kw)
+    _check_vs_oracle(tuned, inst, f"tuned {bl}x{pp}")
+    results = {}
+    for fbl, fpp in ((256, 4), (128, 2)):
+        cache.write_text(f"{key} {fbl} {fpp}\n")
+        assert P.autotune_batch(pay, T, KB, cache_path=str(cache), **kw) == (fbl, fpp)
+        print(f"[batch] forced tile {fbl}x{fpp}", flush=True)
+        res = P.price_batch(pay, T, KB, **kw)
+        _check_vs_oracle(res, inst, f"tile {fbl}x{fpp}")
+        results[(fbl, fpp)] = res
+    # the same paths whatever the tile: sums agree up to their order
+    for a, b in zip(results[(256, 4)], results[(128, 2)]):
+        assert a["sum"] == pytest.approx(b["sum"], rel=1e-12, abs=1e-9)
+    # a cache entry that is not a launchable tile is ignored (tuned again)
+    cache.write_text(f"{key} 100 0\n")
+    bl2, pp2 = P.autotune_batch(pay, T, KB, cache_path=str(cache), **kw)
+    assert bl2 % 64 == 0 and 64 <= bl2 <= 256 and pp2 >= 1
+
+
+def test_sample_instances_equal_single_prices():
+    """Each batch instance prices the same paths as a single pmc_price call
+    with that instance's counter word."""
+    import paper_2108_03076_amd as P
+    inst, ids, T, KB = _sample()
+    n = C4_SAMPLE_PATHS
+    pay = gpu_payoff(CFG)
+    res = P.price_batch(pay, T, KB, **model_kw(CFG), **opts_kw(CFG, n), instance_ids=ids)
+    for i in (0, len(inst) // 2, len(inst) - 1):
+        one = P.price(pay, [int(T[i, 0])], list(KB[i]), **model_kw(CFG), **opts_kw(CFG, n, instance=int(ids[i])))
+        assert res[i]["sum"] == pytest.approx(one["sum"], rel=1e-12, abs=1e-9), i
+
+
+def test_barrier_pins():
+    import paper_2108_03076_amd as P
+    inst, ids, T, KB = _sample()
+    n = C4_SAMPLE_PATHS
+    pay = gpu_payoff(CFG)
+    kw = dict(**model_kw(CFG), **opts_kw(CFG, n), instance_ids=ids)
+    # barrier 0: never hit (prices are positive), so the vanilla call on the
+    # same paths, which the oracle side writes without the IL
+    van = P.price_batch(pay, T, np.stack([KB[:, 0], np.zeros(len(inst))], 1), **kw)
+    worst = 0.0
+    for r, e in zip(van, inst):
+        worst = max(worst, abs(r["price"] - e["vanilla_price"]) / e["vanilla_se"])
+        assert abs(r["price"] - e["vanilla_price"]) <= 0.1 * e["vanilla_se"], (e["id"], r["price"], e)
+    print(f"[batch] vanishing barrier: worst |gpu - vanilla| = {worst:.4f} SE", flush=True)
+    # barrier at or above the spot: knocked out on day 0, exactly zero
+    for b in (100.0, 150.0):
+        out = P.price_batch(pay, T, np.stack([KB[:, 0], np.full(len(inst), b)], 1), **kw)
+        assert all(r["price"] == 0.0 and r["std_err"] == 0.0 for r in out)
+
+
+def test_full_batch_at_tuned_tile():
+    import paper_2108_03076_amd as P
+    from oracle.closed_form import bs_call
+    g = golden()["c4_full"]
+    n = CFG.n_paths
+    assert g["paths"] == n
+    T, K, B = W.c4_instances(1024, 42)
+    tenv = T.reshape(-1, 1)
+    pay = gpu_payoff(CFG)
+    kw = dict(**model_kw(CFG), **opts_kw(CFG, n))
+    bl, pp = P.autotune_batch(pay, tenv, np.stack([K, B], 1), **kw)
+    print(f"[batch] full 1024 x 2^16 at {bl}x{pp}", flush=True)
+    do = P.price_batch(pay, tenv, np.stack([K, B], 1), **kw)
+    van = P.price_batch(pay, tenv, np.stack([K, np.zeros_like(B)], 1), **kw)
+    worst = 0.0
+    for e in g["instances"]:
+        r = do[e["id"]]
+        assert (int(T[e["id"]]), K[e["id"]], B[e["id"]]) == (e["T"], e["K"], e["B"])
+        worst = max(worst, abs(r["price"] - e["price"]) / e["se"])
+        assert abs(r["price"] - e["price"]) <= 0.1 * e["se"], (e["id"], r["price"], e)
+    print(f"[batch] full size: worst |gpu - oracle| = {worst:.4f} SE over {len(g['instances'])} instances",
+          flush=True)
+    z = []
+    for i in range(T.size):
+        # per path the knock-out payoff is at most the vanilla one; the two
+        # batches sum their paths in the same order, and rounded addition is
+        # monotone, so the sums keep the order
+        assert do[i]["sum"] <= van[i]["sum"], i
+        ref = bs_call(100.0, K[i], CFG.rate, 0.2, T[i] / 252.0)
+        z.append((van[i]["price"] - ref) / van[i]["std_err"])
+    z = np.array(z)
+    print(f"[batch] vanilla vs Black-Scholes: max |z| {np.abs(z).max():.2f}, mean z {z.mean():.3f}", flush=True)
+    # 1024 instances: |z| > 4.5 has probability 7e-6 each
+    assert np.abs(z).max() < 4.5
+    assert abs(z.mean()) < 4.5 / math.sqrt(T.size)
+
+
+def test_batch_graph_replays_follow_the_seed():
+    """A batch graph captured for one seed is not replayed for another seed
+    of the same shape (the Philox key is a by-value kernel argument)."""
+    import paper_2108_03076_amd as P
+    cfg = small(CFG)
+    T = np.array([[20], [45], [7], [33], [60], [1], [0], [52]], dtype=np.int32)
+    KB = np.stack([np.linspace(90, 110, 8), np.linspace(60, 95, 8)], 1)
+    n = 2048
+    pay = gpu_payoff(cfg)
+    res = {}
+    for seed in (42, 7, 42):
+        out = P.price_batch(pay, T, KB, **model_kw(cfg), **opts_kw(cfg, n, seed=seed))
+        for i in range(len(T)):
+            one = P.price(pay, [int(T[i, 0])], list(KB[i]), **model_kw(cfg), **opts_kw(cfg, n, seed=seed, instance=i))
+            assert out[i]["sum"] == pytest.approx(one["sum"], rel=1e-12, abs=1e-9), (seed, i)
+        if seed in res:
+            assert [r["sum"] for r in out] == [r["sum"] for r in res[seed]]
+        res[seed] = out
+    assert any(a["sum"] != b["sum"] for a, b in zip(res[42], res[7]) if a["n_slots"] > 0)
+
+
+def test_batch_graph_replays_follow_the_sobol_shape():
+    """Sobol batches of fewer paths than one tile keep the same grid but not
+    the same number of Gray-code bits."""
+    import paper_2108_03076_amd as P
+    cfg = W.C2
+    tenv = np.array([[4], [4]], dtype=np.int32)
+    pay = gpu_payoff(cfg)
+    for n in (100, 200, 100):
+        out = P.price_batch(pay, tenv, np.zeros((2, 0)), **model_kw(cfg), **opts_kw(cfg, n))
+        one = P.price(pay, cfg.tenv, [], **model_kw(cfg), **opts_kw(cfg, n))
+        assert out[0]["sum"] == pytest.approx(one["sum"], rel=1e-12), n

@@ -6,48 +6,17 @@ here are generated for each template environment (loops written out); their
 per-path payoffs must equal the interpreter's bit for bit (the same binary32
 or binary64 operations in the same order) and the oracle's within the FP32
 bars of the parity tests (FP64: 1e-12 relative)."""
-import dataclasses
-
 import numpy as np
 import pytest
 
-import workloads as W
-from gpu_common import gpu_payoff, model_kw, opts_kw, oracle_problem, tie_band
+from cases import PROGRAMS
+from gpu_common import check_band, gpu_payoff, model_kw, opts_kw, oracle_problem, tie_band
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-NESTED = """
-(loopif (lt (model S 0) (real 92.0))
-        (mult (real 1.0) (payoff 0 X Y))
-        (loopif (leq (real 108.0) (model S 0))
-                (mult (sub (model S 0) (real 100.0)) (payoff 0 X Y))
-                (mult (real 0.5) (payoff 0 X Y))
-                (tvar M))
-        (tvar N))
-"""
-
-OPERATORS = """
-(if (and (not (lt (model S 2) (real 95.0))) (leq (now) (t (tvar T))))
-    (mult (max (div (model S 2) (model S (int -1))) (neg (real 0.5))) (payoff (tvar T) X Y))
-    (if (or (eq (model S 1) (real 100.0)) (lt (model S 1) (real 99.0)))
-        (mult (min (model S 1) (real 80.0)) (payoff 1 Y X))
-        (real 0.0)))
-"""
-
-
-def _cfg(il, tvars, tenv, precision="f32"):
-    return dataclasses.replace(W.C3, il=il, tvars=tvars, tenv=tenv, param_labels=[], params=[],
-                               years_per_day=1.0 / 12.0, precision=precision, name="program")
-
-
-CASES = {
-    "nested": _cfg(NESTED, ["N", "M"], [3, 2]),
-    "nested_zero_inner": _cfg(NESTED, ["N", "M"], [4, 0]),
-    "nested_f64": _cfg(NESTED, ["N", "M"], [3, 2], precision="f64"),
-    "operators": _cfg(OPERATORS, ["T"], [4]),
-}
+CASES = PROGRAMS
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -78,6 +47,7 @@ def test_program_engines_modes_and_oracle(name):
     else:
         S = prob.paths(ids)
         band = tie_band(prob, S, 3e-5)
+        check_band(f"programs/{name}", band)
         scale = np.maximum(np.abs(ref), np.max(S, axis=(1, 2)))
         bad = (np.abs(base - ref) > 2e-5 * scale) & ~band
         assert not bad.any(), (np.nonzero(bad)[0][:10], base[bad][:5], ref[bad][:5])
