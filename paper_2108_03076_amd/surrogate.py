@@ -29,6 +29,14 @@ def equicorr(rho):
     return c
 
 
+def box_bounds(box):
+    """Per-input (lo, hi) of the surrogate's box: 3 spots, 3 vols, the
+    pairwise correlation and the number of dates."""
+    lo = [box["spot"][0]] * 3 + [box["vol"][0]] * 3 + [box["rho"][0], box["n_obs"][0]]
+    hi = [box["spot"][1]] * 3 + [box["vol"][1]] * 3 + [box["rho"][1], box["n_obs"][1]]
+    return lo, hi
+
+
 def mc_prices(pay: Payoff, points, n_paths, *, rate, years_per_day, seed, first_id=0, chunk=1 << 15,
               engine="auto"):
     """Monte Carlo prices (and standard errors) of the points [n][8] with one
@@ -92,4 +100,4 @@ def timed_infer(sur: Surrogate, x, reps=20):
     return (time.perf_counter() - t0) / reps * 1e3, y
 
 
-__all__ = ["equicorr", "mc_prices", "train", "errors", "timed_infer", "Context", "Surrogate"]
+__all__ = ["box_bounds", "equicorr", "mc_prices", "train", "errors", "timed_infer", "Context", "Surrogate"]
