@@ -216,6 +216,28 @@ typedef struct pmc_result {
 int pmc_price(pmc_ctx* ctx, const pmc_payoff* p, const int32_t* tenv, const double* params,
               const pmc_gbm* model, const pmc_opts* opts, pmc_result* out);
 
+/* Allocation-free variant of pmc_price, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, checks, random streams
+ * and result as pmc_price with opts.engine = PMC_ENGINE_INTERPRETER and
+ * opts.mode = PMC_MODE_FUSED: the same kernels and grid, so the same sums
+ * bit for bit.  The call allocates no device or pinned memory: its tables,
+ * per-block partials, factorisation status and result live in a static
+ * device array of 4 MiB + 256 bytes per GPU (held until the process ends;
+ * its address is looked up when a context is created), and its uploads and
+ * result copy use pageable host memory.  Every call on one GPU shares that
+ * array and leaves its contents behind; calls that overlap on one GPU (other
+ * threads, contexts or streams) race and must not be made.  opts.payoffs_dev
+ * works as in pmc_price.
+ * Errors: those of pmc_price; PMC_E_UNSUPPORTED for opts.mode =
+ * PMC_MODE_TWO_PHASE, opts.engine = PMC_ENGINE_COMPILED (run-time compiled
+ * code is loaded into newly allocated memory), or tables (bytecode, time and
+ * discount tables, Sobol direction numbers) beyond the array's 2 MiB table
+ * area (e.g. Sobol with more than about 16,000 dimensions); PMC_E_HIP if the
+ * array's address could not be looked up on this device. */
+int pmc_price_noalloc(pmc_ctx* ctx, const pmc_payoff* p, const int32_t* tenv, const double* params,
+                      const pmc_gbm* model, const pmc_opts* opts, pmc_result* out);
+
 /* Batch of instances of one loaded payoff (templated instruments priced
  * with different template values and parameters, Sec. 2 and Sec. 6.2),
  * run as one persistent launch over (instance, path-tile) work items taken

@@ -10,7 +10,7 @@ Python binding (argument marshalling only); torch supplies device memory
 and streams.
 """
 from ._lib import (EXPORTED, LIB_PATH, Context, PmcError, Payoff, autotune_batch, eval_paths, gen_paths,
-                   lib, load_payoff, price, price_batch, risk_batch, Pricer, Surrogate)
+                   lib, load_payoff, price, price_batch, price_noalloc, risk_batch, Pricer, Surrogate)
 
-__all__ = ["Context", "Payoff", "PmcError", "price", "price_batch", "risk_batch", "autotune_batch", "gen_paths",
+__all__ = ["Context", "Payoff", "PmcError", "price", "price_batch", "price_noalloc", "risk_batch", "autotune_batch", "gen_paths",
            "eval_paths", "load_payoff", "Pricer", "Surrogate", "lib", "LIB_PATH", "EXPORTED"]

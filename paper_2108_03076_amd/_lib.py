@@ -109,6 +109,8 @@ _sig = {
     "pmc_payoff_grid": (_i, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _i, C.POINTER(_i), C.POINTER(_i)]),
     "pmc_price": (_i, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(Gbm), C.POINTER(Opts),
                        C.POINTER(Result)]),
+    "pmc_price_noalloc": (_i, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(Gbm),
+                               C.POINTER(Opts), C.POINTER(Result)]),
     "pmc_price_batch": (_i, [_vp, _vp, C.POINTER(Batch), C.POINTER(Gbm), C.POINTER(Opts), C.POINTER(Result)]),
     "pmc_risk_batch": (_i, [_vp, _vp, C.POINTER(Batch), C.POINTER(Gbm), C.POINTER(Opts), C.POINTER(RiskOpts),
                             C.POINTER(Greeks)]),
@@ -300,6 +302,19 @@ def price(payoff: Payoff, tenv=(), params=(), *, spot, vol, corr=None, rate=0.03
     p, pp = _dbl(params if len(params) else [0.0])
     r = Result()
     payoff.ctx.check(lib.pmc_price(payoff.ctx.h, payoff.h, tp, pp, C.byref(g), C.byref(o), C.byref(r)))
+    return r.as_dict()
+
+
+def price_noalloc(payoff: Payoff, tenv=(), params=(), *, spot, vol, corr=None, rate=0.03, years_per_day=1.0,
+                  **opts):
+    """pmc_price_noalloc: pmc_price by the interpreter, fused, with no device
+    allocation (the library's static per-device scratch)."""
+    g, keep = make_model(spot, vol, corr, rate, years_per_day)
+    o = make_opts(**opts)
+    t, tp = _i32(tenv if len(tenv) else [0])
+    p, pp = _dbl(params if len(params) else [0.0])
+    r = Result()
+    payoff.ctx.check(lib.pmc_price_noalloc(payoff.ctx.h, payoff.h, tp, pp, C.byref(g), C.byref(o), C.byref(r)))
     return r.as_dict()
 
 

@@ -116,6 +116,10 @@ struct pmc_ctx {
     int engine = 0;
   } prepared;
   std::vector<uint8_t> key_buf;   // scratch for a call's key
+  // The device address of the allocation-free call's scratch on this
+  // device (null, with the reason, if the lookup failed).
+  void* scratch = nullptr;
+  std::string scratch_err;
 };
 
 static uint64_t next_payoff_serial() {
@@ -177,6 +181,12 @@ extern "C" int pmc_ctx_create(int device, void* stream, pmc_ctx** out) {
   if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail("hipGetDeviceProperties", e);
   c->n_cu = prop.multiProcessorCount;
   c->device_name = prop.gcnArchName;
+  // Set-up of the allocation-free call: the scratch's address on this
+  // device, looked up (once per device) while the device is current.
+  if ((e = scratch_address(device, &c->scratch)) != hipSuccess) {
+    c->scratch = nullptr;
+    c->scratch_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+  }
   // Start and intermediate markers only take times: no system-scope cache
   // write-back and invalidation when they are reached (which would also
   // leave the following kernel a cold L2).  The end marker, which the host
@@ -596,6 +606,26 @@ int first_bad(pmc_ctx* c, int n_inst) {
   return -1;
 }
 
+// One instrument's result from its FP64 path sums.
+pmc_result make_result(double2 sums, uint64_t n_paths, int n_slots, int mode_used, double ms, double gen_ms,
+                       double eval_ms) {
+  const double N = (double)n_paths;
+  pmc_result r{};
+  r.sum = sums.x;
+  r.sum_sq = sums.y;
+  r.n_paths = n_paths;
+  r.price = r.sum / N;
+  const double var = N > 1 ? std::max(0.0, (r.sum_sq - r.sum * r.sum / N) / (N - 1.0)) : 0.0;
+  r.std_err = std::sqrt(var / N);
+  r.n_slots = n_slots;
+  r.path_dates = n_paths * (uint64_t)n_slots;
+  r.mode_used = mode_used;
+  r.ms = ms;
+  r.gen_ms = gen_ms;
+  r.eval_ms = eval_ms;
+  return r;
+}
+
 // Reads the results the kernels wrote to host memory; the caller has
 // synchronized with the launch.
 int finish(pmc_ctx* c, int n_inst, const uint64_t* n_paths, const int* n_slots, int mode_used, double ms,
@@ -603,23 +633,8 @@ int finish(pmc_ctx* c, int n_inst, const uint64_t* n_paths, const int* n_slots, 
   const int bad = first_bad(c, n_inst);
   if (bad >= 0) return fail(c, PMC_E_NOT_PD, "correlation matrix of instance " + std::to_string(bad) + " is not positive definite");
   const double2* res = (const double2*)c->results.p;
-  for (int i = 0; i < n_inst; ++i) {
-    const double N = (double)n_paths[i];
-    pmc_result r{};
-    r.sum = res[i].x;
-    r.sum_sq = res[i].y;
-    r.n_paths = n_paths[i];
-    r.price = r.sum / N;
-    const double var = N > 1 ? std::max(0.0, (r.sum_sq - r.sum * r.sum / N) / (N - 1.0)) : 0.0;
-    r.std_err = std::sqrt(var / N);
-    r.n_slots = n_slots[i];
-    r.path_dates = n_paths[i] * (uint64_t)n_slots[i];
-    r.mode_used = mode_used;
-    r.ms = ms;
-    r.gen_ms = gen_ms;
-    r.eval_ms = eval_ms;
-    out[i] = r;
-  }
+  for (int i = 0; i < n_inst; ++i)
+    out[i] = make_result(res[i], n_paths[i], n_slots[i], mode_used, ms, gen_ms, eval_ms);
   return PMC_OK;
 }
 
@@ -947,6 +962,121 @@ extern "C" int pmc_eval_paths(pmc_ctx* c, const pmc_payoff* p, const int32_t* te
   HIP_TRY(c, hipSetDevice(c->device));
   return o->precision == PMC_FP64 ? price_one<double>(c, p, tenv, params, m, o, out, paths_dev, true)
                                   : price_one<float>(c, p, tenv, params, m, o, out, paths_dev, true);
+}
+
+// ------------------------------------------------ allocation-free call ---
+namespace {
+
+// One fused pricing by the precompiled interpreter kernel, with every
+// device buffer in the per-device scratch: the tables are copied into its
+// table area, the kernel writes its per-block partials and factorisation
+// status there, the finishing kernel the (sum, sum of squares), which is
+// copied back to the host.  Nothing in the scratch has to start at zero.
+template <typename T>
+int price_noalloc_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double* params,
+                      const pmc_gbm* m, const pmc_opts* o, pmc_result* out) {
+  const Program& P = p->prog;
+  InstanceIn in{tenv, params, m->spot, m->vol, m->corr, o->instance};
+  int st = check_instance(c, P, in);
+  if (st != PMC_OK) return st;
+  Tables<T> tb;
+  st = build_instance<T>(c, P, *m, *o, in, 0, tb);
+  if (st != PMC_OK) return st;
+  const int A = (int)P.assets.size();
+  const int block = o->block ? o->block : 256;
+  const uint64_t N = o->n_paths;
+  const int n_slots = tb.desc[0].n_slots;
+  const uint32_t tiles = (uint32_t)((N + (uint64_t)block - 1) / (uint64_t)block);
+  tb.desc[0].n_tiles = tiles;
+  tb.desc[0].first_item = 0;
+  Pack pk;
+  std::vector<T> consts(P.consts.size());
+  for (size_t i = 0; i < consts.size(); ++i) consts[i] = (T)P.consts[i];
+  const size_t o_code = pk.add(P.code.data(), P.code.size() * sizeof(Instr));
+  const size_t o_consts = pk.add(consts.data(), consts.size() * sizeof(T));
+  const size_t o_desc = pk.add(tb.desc.data(), tb.desc.size() * sizeof(InstDesc));
+  const size_t o_itab = pk.add(tb.itab.data(), tb.itab.size() * sizeof(int32_t));
+  const size_t o_rtab = pk.add(tb.rtab.data(), tb.rtab.size() * sizeof(T));
+  const size_t o_corr = pk.add(tb.corr.data(), tb.corr.size() * sizeof(double));
+  const int dims = std::max(1, tb.max_dims);
+  size_t o_sobol = 0;
+  if (o->rng == PMC_RNG_SOBOL) {
+    if (dims > 20000) return fail(c, PMC_E_UNSUPPORTED, "Sobol needs more than 20000 dimensions");
+    const unsigned int* v = nullptr;
+    if (rocrand_get_direction_vectors32(&v, ROCRAND_DIRECTION_VECTORS_32_JOEKUO6) != ROCRAND_STATUS_SUCCESS || !v)
+      return fail(c, PMC_E_HIP, "Sobol direction numbers unavailable");
+    o_sobol = pk.add(v, (size_t)std::max(dims, 64) * 32 * sizeof(uint32_t));
+  }
+  if (pk.bytes.size() > kScratchTables)
+    return fail(c, PMC_E_UNSUPPORTED, "the allocation-free call's tables need " + std::to_string(pk.bytes.size()) +
+                                          " bytes; its scratch holds " + std::to_string(kScratchTables));
+  uint8_t* const sc = (uint8_t*)c->scratch;
+  uint8_t* const tab = sc + kScratchHead + (size_t)kScratchPartials * sizeof(double2);
+  McLaunch L{};
+  L.code = (const Instr*)(tab + o_code);
+  L.consts = tab + o_consts;
+  L.desc = (const InstDesc*)(tab + o_desc);
+  L.itab = (const int32_t*)(tab + o_itab);
+  L.rtab = tab + o_rtab;
+  L.chol_in = (const double*)(tab + o_corr);
+  L.chol = L.chol_in;   // not read: every block factors the matrix itself
+  L.factor = 1;
+  L.status = (int*)(sc + sizeof(double2));
+  L.result = (double2*)sc;
+  L.partial = (double2*)(sc + kScratchHead);
+  L.k0 = (uint32_t)(o->seed & 0xFFFFFFFFull);
+  L.k1 = (uint32_t)(o->seed >> 32);
+  L.n_assets = A;
+  L.n_regs = P.n_regs;
+  L.ppt = 1;
+  L.n_work = (int)tiles;
+  L.payoff_out = o->payoffs_dev;
+  if (o->rng == PMC_RNG_SOBOL) {
+    L.sobol = (const uint32_t*)(tab + o_sobol);
+    L.sobol_bits = sobol_bits(N);
+    L.sobol_dims = dims;   // no high-part table: words come from the direction numbers
+  }
+  // the interpreter's grid of pmc_price, within the scratch's partials
+  pmc_opts oi = *o;
+  oi.engine = PMC_ENGINE_INTERPRETER;
+  EngineLaunch e;
+  st = resolve_engine(c, p, &oi, sizeof(T) == 8 ? 1 : 0, false, L, (int)tiles, block, 1, (int64_t)n_slots * A, 0,
+                      nullptr, e);
+  if (st != PMC_OK) return st;
+  if (e.grid > kScratchPartials) e.grid = balanced_grid(e.grid, kScratchPartials);
+  HIP_TRY(c, hipMemcpyAsync(tab, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+  st = run_engine(c, e, L, c->evk[2]);
+  if (st != PMC_OK) return st;
+  HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+  struct { double2 sums; int status; } head{};
+  HIP_TRY(c, hipMemcpyAsync(&head, sc, sizeof(double2) + sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (head.status) return fail(c, PMC_E_NOT_PD, "correlation matrix is not positive definite");
+  float ms = 0, eval_ms = 0;
+  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  HIP_TRY(c, hipEventElapsedTime(&eval_ms, c->ev0, c->evk[2]));
+  *out = make_result(head.sums, N, n_slots, PMC_MODE_FUSED, ms, 0.0, eval_ms);
+  out->engine_used = PMC_ENGINE_INTERPRETER;
+  return PMC_OK;
+}
+
+}  // namespace
+
+extern "C" int pmc_price_noalloc(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double* params,
+                                 const pmc_gbm* m, const pmc_opts* o, pmc_result* out) {
+  if (!c || !p || !out) return fail(c, PMC_E_ARG, "null argument");
+  int st = check_model(c, p->prog, m);
+  if (st == PMC_OK) st = check_opts(c, o);
+  if (st != PMC_OK) return st;
+  if (o->mode == PMC_MODE_TWO_PHASE)
+    return fail(c, PMC_E_UNSUPPORTED, "the allocation-free call generates paths in registers (fused) only");
+  if (o->engine == PMC_ENGINE_COMPILED)
+    return fail(c, PMC_E_UNSUPPORTED, "the allocation-free call runs the precompiled interpreter only");
+  if (!c->scratch) return fail(c, PMC_E_HIP, c->scratch_err);
+  HIP_TRY(c, hipSetDevice(c->device));
+  return o->precision == PMC_FP64 ? price_noalloc_one<double>(c, p, tenv, params, m, o, out)
+                                  : price_noalloc_one<float>(c, p, tenv, params, m, o, out);
 }
 
 namespace {

@@ -66,4 +66,18 @@ hipError_t launch_sobol_hi(const uint32_t* sobol, uint32_t* hi, int n_rows, int 
 int mc_occupancy(int precision, int rng, int n_assets, int n_regs, int block);
 int mc_occupancy_jit(hipFunction_t f, int block);
 
+// Device scratch of the allocation-free pricing call: one array per device,
+// of kScratchBytes, held until the process ends.  Layout: the result
+// (sum, sum of squares) and the factorisation status in the first
+// kScratchHead bytes, then kScratchPartials per-block partials, then the
+// call's tables (bytecode, descriptors, time and discount tables,
+// correlation, Sobol direction numbers) in the rest.
+constexpr size_t kScratchHead = 256;
+constexpr int kScratchPartials = 1 << 16;
+constexpr size_t kScratchTables = size_t(2) << 20;
+constexpr size_t kScratchBytes = kScratchHead + size_t(kScratchPartials) * 16 + kScratchTables;
+// The device address of the scratch on `device`, which must be the current
+// device.  Looked up once per device (later calls return the kept address).
+hipError_t scratch_address(int device, void** out);
+
 }  // namespace pmc

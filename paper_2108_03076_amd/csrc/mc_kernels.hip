@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "kernels.h"
 #include "mc_engine.h"
@@ -144,7 +146,35 @@ int occ_t(int block, int n_regs) {
   return n > 0 ? n : 1;
 }
 
+// The allocation-free call's scratch.  In host code `scratch` names a
+// host-side stand-in, not device memory: only the address that
+// hipGetSymbolAddress returns for the current device is ever passed to a
+// kernel or a copy.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 }  // namespace
+
+hipError_t scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;   // per device
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p || ((uintptr_t)p & 255u)) return hipErrorInvalidSymbol;
+  addr[device] = p;
+  *out = p;
+  return hipSuccess;
+}
 
 hipError_t launch_mc(int precision, int rng, bool mem, const McLaunch& a, int grid, int block,
                      hipStream_t s) {
