@@ -433,6 +433,8 @@ def main():
         for i in range(T.size):
             r = P.price(pay4, [int(T[i])], [K[i], B[i]], **dict(kw4, instance=i))
             dev_ms += r["ms"]
+            if i % 256 == 255:
+                print(f"[bench] C4 separate calls: {i + 1} done", file=sys.stderr, flush=True)
         wall = time.perf_counter() - t0
         extra["C4_separate_pmc_price_calls"] = {"wall_s": wall, "device_ms": dev_ms,
                                                 "path_dates_per_s": pd4 / wall,

@@ -187,6 +187,18 @@ typedef struct pmc_opts {
                               double[N] (FP64); NULL to skip */
   int block;               /* threads per block, 0 = default (256) */
   int engine;              /* PMC_ENGINE_*: how the payoff runs on the device */
+  /* Optional price history (Sec. 4.1: the environment is historical data up
+   * to the current time and simulated data after it): history[a *
+   * history_len + j] is the observed price of asset a on day t_now -
+   * history_len + 1 + j, so the history ends on the current day t_now (>= 0).
+   * A day up to t_now then reads the history (days before its first one read
+   * its first price); the simulation starts on day t_now from the history's
+   * last prices (model.spot is not used) and covers the days after it.  The
+   * discount function stays d(day) = exp(-rate * day * years_per_day)
+   * (Thm. 5).  NULL: days up to 0 read model.spot and the simulation starts
+   * on day 0.  Host memory, read during the call; prices finite and > 0. */
+  const double* history;
+  int32_t history_len;
 } pmc_opts;
 
 typedef struct pmc_result {
@@ -281,7 +293,8 @@ int pmc_autotune_batch(pmc_ctx* ctx, const pmc_payoff* p, const pmc_batch* batch
  * (V+ - 2V + V-) / h_a^2 and vega_a = (V+ - V-) / 2k.  out[n_inst]; entries
  * beyond A are zero; ms is the device time of the whole launch.
  * Errors: those of pmc_price_batch; PMC_E_ARG if 0 < rel_spot_bump < 1 and
- * 0 < abs_vol_bump < sigma_a do not hold. */
+ * 0 < abs_vol_bump < sigma_a do not hold; PMC_E_UNSUPPORTED with a price
+ * history (opts.history: the simulation would not start from the spots). */
 typedef struct pmc_risk_opts {
   double rel_spot_bump;
   double abs_vol_bump;
@@ -347,6 +360,22 @@ int pmc_mlp_train_epoch(pmc_mlp* m, const float* x_dev, const float* y_dev, int6
                         const pmc_train_opts* o, double* mean_loss);
 /* Forward pass: y_dev[n] prices (float) for raw inputs x_dev[n][n_in]. */
 int pmc_mlp_infer(pmc_mlp* m, const float* x_dev, float* y_dev, int64_t n);
+/* Prices from the surrogate with Monte Carlo as the fallback: point i, with
+ * raw inputs x[i][n_in] (host memory), is priced by the network when every
+ * input lies in the network's input box [lo, hi] (the box it was created
+ * with, which its training data covers), and otherwise by Monte Carlo:
+ * instance i of `batch` (n_inst = n, in the same order; the same layout and
+ * rules as pmc_price_batch) priced with payoff p, `model` and `opts`, all
+ * out-of-box instances in one pmc_price_batch launch.  An instance keeps its
+ * stream id (batch->instance_ids[i], else i), so a fallback price equals the
+ * one pmc_price_batch gives that instance within any batch.  price_out[n];
+ * std_err_out[n] (optional) receives the Monte Carlo standard error, 0 for a
+ * network price; route_out[n] (optional) 0 for the network, 1 for Monte
+ * Carlo.  Errors: PMC_E_ARG (n_inst != n, missing arrays), and those of
+ * pmc_mlp_infer and pmc_price_batch. */
+int pmc_mlp_price(pmc_mlp* m, const double* x, int64_t n, const pmc_payoff* p, const pmc_batch* batch,
+                  const pmc_gbm* model, const pmc_opts* opts, double* price_out, double* std_err_out,
+                  int* route_out);
 /* Loss and gradients of the mean squared error over n samples (1 <= n <=
  * 65536) at the current weights (FP32 gradients, host out, same order as
  * get_params). */

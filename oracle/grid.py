@@ -54,12 +54,13 @@ def reads(e, delta, t0_lo=0, t0_hi=0):
     return model_days, payoff_days
 
 
-def slots(e, delta, asset_labels):
-    """Sorted unique days > 0 read for any model asset (the simulation grid)."""
+def slots(e, delta, asset_labels, after=0):
+    """Sorted unique days > after read for any model asset (the simulation
+    grid; `after` is the last day of a given price history, else 0)."""
     md, _ = reads(e, delta)
     days = set()
     for lab in asset_labels:
-        days |= {d for d in md.get(lab, ()) if d > 0}
+        days |= {d for d in md.get(lab, ()) if d > after}
     return sorted(days)
 
 

@@ -8,6 +8,15 @@ Per path the steps are: random words -> uniforms -> normals -> correlated
 normals -> GBM prices on the simulated days -> payoff value by the semantics
 of Fig. 3 with t0 = 0 and the current time t = t_now -> one sum over paths.
 
+Pricing at a current time with a price history (Sec. 4.1): the environment
+is the union of historical data, for the days up to the current day, and
+simulated data after it.  Given history[a][j], the price of asset a on day
+t_now - n + 1 + j (j < n, so the history ends on the current day), a day up
+to t_now reads the history (days before its first one read the first
+value), and the simulation starts on day t_now from the history's last
+prices; the discount function d stays the one of day 0 (Thm. 5).  Without a
+history, days up to 0 read the spot and the simulation starts on day 0.
+
 The estimate is the sample mean; the standard error is the sample standard
 deviation (denominator N-1) over sqrt(N).  Sums use math.fsum.
 """
@@ -28,7 +37,7 @@ class Problem:
 
     def __init__(self, il, *, asset_labels, param_labels=(), params=(), tenv=None,
                  spot, vol, corr=None, rate, years_per_day, rng="philox", seed=42,
-                 instance=0, precision="f32", t_now=0, parties=("X", "Y")):
+                 instance=0, precision="f32", t_now=0, parties=("X", "Y"), history=None):
         self.ast = parse(il) if isinstance(il, str) else il
         self.asset_labels = list(asset_labels)
         self.param_labels = list(param_labels)
@@ -48,7 +57,18 @@ class Problem:
         self.precision = precision
         self.t_now = int(t_now)
         self.p1, self.p2 = parties
-        self.days = grid.slots(self.ast, self.delta, self.asset_labels)
+        self.history = None
+        self.start = 0
+        self.sim_spot = self.spot
+        if history is not None:
+            h = np.asarray(history, dtype=np.float64).reshape(A, -1)
+            if self.t_now < 0 or h.shape[1] < 1 or not np.all(np.isfinite(h) & (h > 0)):
+                raise ValueError("a history needs t_now >= 0 and finite positive prices")
+            self.history = h
+            self.hist_first = self.t_now - h.shape[1] + 1
+            self.start = self.t_now
+            self.sim_spot = h[:, -1].copy()
+        self.days = grid.slots(self.ast, self.delta, self.asset_labels, after=self.start)
         self.slot_of = {d: s for s, d in enumerate(self.days)}
         self.d = discount(self.rate, self.ypd)
 
@@ -81,19 +101,24 @@ class Problem:
     def paths(self, path_ids):
         """S[p][slot][asset] in binary64."""
         z = self.normals(path_ids)
-        return gbm_paths(z, self.days, self.ypd, self.rate, self.spot, self.vol, self.L)
+        return gbm_paths(z, self.days, self.ypd, self.rate, self.sim_spot, self.vol, self.L, start=self.start)
 
     def env(self, S_path):
-        """rho(label, day) for one path: day <= 0 is the spot (flat history),
-        a parameter observable is its constant value."""
+        """rho(label, day) for one path: a day up to the simulation's start
+        is history (the spot, flat, without a given history), a later day
+        the path; a parameter observable is its constant value."""
         idx = {lab: a for a, lab in enumerate(self.asset_labels)}
+        h = self.history
 
         def rho(label, day):
             if label in self.params:
                 return self.params[label]
             a = idx[label]
-            if day <= 0:
-                return float(self.spot[a])
+            if day <= self.start:
+                if h is None:
+                    return float(self.spot[a])
+                j = min(max(day - self.hist_first, 0), h.shape[1] - 1)
+                return float(h[a][j])
             return float(S_path[self.slot_of[day]][a])
 
         return rho

@@ -13,8 +13,10 @@ fixes (each reading is listed in the design notes):
 * model: risk-neutral geometric Brownian motion with constant rate r and
   volatilities sigma_a, no dividends.  Between consecutive simulated days
   the log-price moves by (r - sigma_a^2/2) dt + sigma_a sqrt(dt) w_a, with
-  dt = (day_s - day_{s-1}) * years_per_day and day_{-1} = 0; the price is
-  S0_a exp(x_a).  This is exact in distribution at the grid dates.
+  dt = (day_s - day_{s-1}) * years_per_day and day_{-1} = the day the
+  simulation starts from (0, or the current day when a price history is
+  given, Sec. 4.1); the price is S0_a exp(x_a) with S0 the price on that
+  day.  This is exact in distribution at the grid dates.
 * discount: d(day) = exp(-r * day * years_per_day).
 """
 from __future__ import annotations
@@ -57,13 +59,14 @@ def cholesky(a):
     return np.array(L)
 
 
-def step_coefficients(days, years_per_day, rate, vol):
+def step_coefficients(days, years_per_day, rate, vol, start=0):
     """Per-slot drift and diffusion: m[s][a] = (r - sigma_a^2/2) dt_s,
-    v[s][a] = sigma_a sqrt(dt_s), dt_s = (day_s - day_{s-1}) * years_per_day."""
+    v[s][a] = sigma_a sqrt(dt_s), dt_s = (day_s - day_{s-1}) * years_per_day,
+    day_{-1} = start."""
     vol = np.asarray(vol, dtype=np.float64)
     m = np.zeros((len(days), vol.size))
     v = np.zeros((len(days), vol.size))
-    prev = 0
+    prev = start
     for s, day in enumerate(days):
         dt = (day - prev) * years_per_day
         m[s] = (rate - 0.5 * vol * vol) * dt
@@ -72,11 +75,12 @@ def step_coefficients(days, years_per_day, rate, vol):
     return m, v
 
 
-def gbm_paths(z, days, years_per_day, rate, spot, vol, L):
-    """Prices S[p][s][a] from normals z[p][s][a] (binary64)."""
+def gbm_paths(z, days, years_per_day, rate, spot, vol, L, start=0):
+    """Prices S[p][s][a] from normals z[p][s][a] (binary64); spot is the
+    price on day `start`, where the simulation begins."""
     z = np.asarray(z, dtype=np.float64)
     spot = np.asarray(spot, dtype=np.float64)
-    m, v = step_coefficients(days, years_per_day, rate, vol)
+    m, v = step_coefficients(days, years_per_day, rate, vol, start)
     n_paths, n_slots, n_assets = z.shape
     S = np.zeros_like(z)
     x = np.zeros((n_paths, n_assets))

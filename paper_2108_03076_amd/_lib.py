@@ -53,7 +53,7 @@ class Opts(C.Structure):
     _fields_ = [("n_paths", C.c_uint64), ("rng", C.c_int), ("seed", C.c_uint64), ("instance", C.c_uint32),
                 ("precision", C.c_int), ("t_now", C.c_int32), ("party_from", C.c_char_p),
                 ("party_to", C.c_char_p), ("mode", C.c_int), ("payoffs_dev", C.c_void_p), ("block", C.c_int),
-                ("engine", C.c_int)]
+                ("engine", C.c_int), ("history", C.POINTER(C.c_double)), ("history_len", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -130,6 +130,8 @@ _sig = {
     "pmc_mlp_set_params": (_i, [_vp, C.POINTER(C.c_float)]),
     "pmc_mlp_train_epoch": (_i, [_vp, _vp, _vp, _i64, C.POINTER(TrainOpts), C.POINTER(C.c_double)]),
     "pmc_mlp_infer": (_i, [_vp, _vp, _vp, _i64]),
+    "pmc_mlp_price": (_i, [_vp, C.POINTER(C.c_double), _i64, _vp, C.POINTER(Batch), C.POINTER(Gbm),
+                           C.POINTER(Opts), C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "pmc_mlp_loss_grad": (_i, [_vp, _vp, _vp, _i64, C.POINTER(C.c_double), C.POINTER(C.c_float)]),
 }
 EXPORTED = []
@@ -289,9 +291,18 @@ def make_model(spot, vol, corr=None, rate=0.03, years_per_day=1.0):
 
 
 def make_opts(n_paths, rng="philox", seed=42, instance=0, precision="f32", t_now=0, parties=("X", "Y"),
-              mode="auto", payoffs=None, block=0, engine="auto"):
+              mode="auto", payoffs=None, block=0, engine="auto", history=None):
+    """Opts struct; history (optional) is [n_assets][n] prices on days
+    t_now - n + 1 .. t_now (kept alive by the struct)."""
+    hp, hl, keep = None, 0, None
+    if history is not None:
+        keep = np.ascontiguousarray(np.asarray(history, dtype=np.float64))
+        hl = int(keep.shape[-1]) if keep.ndim else 1
+        hp = keep.ctypes.data_as(C.POINTER(C.c_double))
     o = Opts(int(n_paths), RNG[rng], int(seed), int(instance), PREC[precision], int(t_now),
-             parties[0].encode(), parties[1].encode(), MODE[mode], _ptr(payoffs), int(block), ENGINE[engine])
+             parties[0].encode(), parties[1].encode(), MODE[mode], _ptr(payoffs), int(block), ENGINE[engine],
+             hp, hl)
+    o._history = keep
     return o
 
 
@@ -395,6 +406,30 @@ class Surrogate:
 
     def infer(self, x, y):
         self.ctx.check(lib.pmc_mlp_infer(self.h, _ptr(x), _ptr(y), int(y.numel())))
+
+    def price(self, x, payoff, tenv, params, *, spot, vol, corr=None, rate=0.03, years_per_day=1.0,
+              per_instance_model=False, instance_ids=None, **opts):
+        """pmc_mlp_price: the network's price for points inside its input box,
+        Monte Carlo (instance i of the batch tenv/params/model) outside it.
+        Returns (price [n], Monte Carlo standard error [n] (0 for network
+        prices), route [n]: 0 network, 1 Monte Carlo)."""
+        xa = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        n = int(xa.shape[0])
+        b, nb, keep = _batch(payoff, tenv, params, spot, vol, corr, per_instance_model, instance_ids)
+        A = len(payoff.assets)
+        if per_instance_model:
+            g, keep2 = make_model([100.0] * A, [0.0] * A, None, rate, years_per_day)
+        else:
+            g, keep2 = make_model(spot, vol, corr, rate, years_per_day)
+        o = make_opts(**opts)
+        pr = np.zeros(n)
+        se = np.zeros(n)
+        route = np.zeros(n, dtype=np.int32)
+        self.ctx.check(lib.pmc_mlp_price(self.h, xa.ctypes.data_as(C.POINTER(C.c_double)), n, payoff.h, C.byref(b),
+                                         C.byref(g), C.byref(o), pr.ctypes.data_as(C.POINTER(C.c_double)),
+                                         se.ctypes.data_as(C.POINTER(C.c_double)),
+                                         route.ctypes.data_as(C.POINTER(C.c_int))))
+        return pr, se, route
 
     def loss_grad(self, x, y):
         g = np.zeros(self.n_params, dtype=np.float32)

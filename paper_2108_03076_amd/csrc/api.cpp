@@ -377,6 +377,8 @@ int check_opts(pmc_ctx* c, const pmc_opts* o) {
   if (!o->party_from || !o->party_to) return fail(c, PMC_E_ARG, "null party name");
   if (o->block != 0 && (o->block % 64 != 0 || o->block > 256 || o->block < 64))
     return fail(c, PMC_E_ARG, "block must be 64, 128, 192 or 256");
+  if (o->history && (o->history_len < 1 || o->history_len > (1 << 20) || o->t_now < 0))
+    return fail(c, PMC_E_ARG, "a price history needs 1 <= history_len <= 2^20 and t_now >= 0");
   if (o->mode < 0 || o->mode > 2) return fail(c, PMC_E_ARG, "bad mode");
   if (o->engine < 0 || o->engine > 2) return fail(c, PMC_E_ARG, "bad engine");
   return PMC_OK;
@@ -392,6 +394,7 @@ struct Tables {
   int max_dims = 0;          // largest slots * assets
   int64_t path_dates = 0;
   std::vector<int> n_slots;
+  int32_t hist_off = -1;     // a given price history, shared by the instances
 };
 
 // Tables shared by every instance with the same template environment
@@ -414,7 +417,7 @@ int build_instance(pmc_ctx* c, const Program& P, const pmc_gbm& m, const pmc_opt
   } else {
     Grid g;
     std::string err;
-    int st = plan(P, in.tenv, g, err);
+    int st = plan(P, in.tenv, g, err, o.history ? o.t_now : 0);
     if (st != PMC_OK) return fail(c, st, err);
     gt.tt_off = (int32_t)tb.itab.size();
     tb.itab.insert(tb.itab.end(), g.tt.begin(), g.tt.end());
@@ -436,9 +439,10 @@ int build_instance(pmc_ctx* c, const Program& P, const pmc_gbm& m, const pmc_opt
     // d(day) = exp(-r * day * years_per_day)
     gt.disc_off = (int32_t)tb.rtab.size();
     for (int32_t day = 0; day <= g.horizon; ++day) tb.rtab.push_back((T)std::exp(-m.rate * (double)day * m.years_per_day));
-    // per slot: dt, sqrt(dt) with dt = (day_s - day_{s-1}) * years_per_day
+    // per slot: dt, sqrt(dt) with dt = (day_s - day_{s-1}) * years_per_day,
+    // from the day the simulation starts
     gt.slot_off = (int32_t)tb.rtab.size();
-    int32_t prev = 0;
+    int32_t prev = g.sim_from;
     for (int32_t day : g.days) {
       const double dt = (double)(day - prev) * m.years_per_day;
       tb.rtab.push_back((T)dt);
@@ -462,7 +466,26 @@ int build_instance(pmc_ctx* c, const Program& P, const pmc_gbm& m, const pmc_opt
   d.model_off = (int32_t)tb.rtab.size();
   for (int a = 0; a < A; ++a) tb.rtab.push_back((T)(m.rate - 0.5 * in.vol[a] * in.vol[a]));
   for (int a = 0; a < A; ++a) tb.rtab.push_back((T)in.vol[a]);
-  for (int a = 0; a < A; ++a) tb.rtab.push_back((T)in.spot[a]);
+  // the prices the simulation starts from: the spot, or the history's last
+  const int32_t L = o.history_len;
+  for (int a = 0; a < A; ++a) tb.rtab.push_back((T)(o.history ? o.history[(size_t)a * L + L - 1] : in.spot[a]));
+  if (o.history) {
+    if (tb.hist_off < 0) {
+      for (size_t i = 0; i < (size_t)A * L; ++i)
+        if (!finite(o.history[i]) || !(o.history[i] > 0)) return fail(c, PMC_E_ARG, "history prices must be finite and > 0");
+      tb.hist_off = (int32_t)tb.rtab.size();
+      for (size_t i = 0; i < (size_t)A * L; ++i) tb.rtab.push_back((T)o.history[i]);
+    }
+    d.sim_from = o.t_now;
+    d.hist_off = tb.hist_off;
+    d.hist_first = o.t_now - L + 1;
+    d.n_hist = L;
+  } else {   // days up to 0 read the spot
+    d.sim_from = 0;
+    d.hist_off = d.model_off + 2 * A;
+    d.hist_first = 0;
+    d.n_hist = 1;
+  }
   d.chol_off = (int32_t)tb.corr.size();
   for (int i = 0; i < A; ++i)
     for (int j = 0; j < A; ++j) tb.corr.push_back(in.corr ? in.corr[i * A + j] : (i == j ? 1.0 : 0.0));
@@ -776,6 +799,11 @@ bool call_key(std::vector<uint8_t>& k, const pmc_payoff* p, int real_size, const
   put(k, o->t_now); put(k, o->mode); put(k, o->payoffs_dev); put(k, o->block); put(k, o->engine);
   put_bytes(k, o->party_from, std::strlen(o->party_from) + 1);
   put_bytes(k, o->party_to, std::strlen(o->party_to) + 1);
+  put(k, (uint8_t)(o->history != nullptr));
+  if (o->history) {
+    put(k, o->history_len);
+    put_bytes(k, o->history, A * (size_t)o->history_len * sizeof(double));
+  }
   return true;
 }
 
@@ -846,11 +874,12 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   } else if (mode == PMC_MODE_AUTO) {
     // fused unless the window would regenerate much more than one path
     std::vector<int32_t> key(tenv, tenv + P.tvars.size());
+    key.push_back(o->history ? o->t_now : 0);   // the grid starts after the history
     auto it = p->fused_cost.find(key);
     if (it == p->fused_cost.end()) {
       Grid g;
       std::string err;
-      plan(P, tenv, g, err);
+      plan(P, tenv, g, err, o->history ? o->t_now : 0);
       it = p->fused_cost.emplace(key, fused_generation_cost(P, g, A, 1 << 22)).first;
     }
     const int64_t cost = it->second;
@@ -895,8 +924,10 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   const bool two_phase = mode == PMC_MODE_TWO_PHASE;
   // the pricing kernel is generated for this template environment (a
   // program without template variables has one, the empty one)
+  // (with a price history, the generic kernel: a generated one fixes the
+  // grid, which then also depends on the current day)
   static const int32_t kNoTenv[1] = {0};
-  const int32_t* env = tenv ? tenv : kNoTenv;
+  const int32_t* env = o->history ? nullptr : tenv ? tenv : kNoTenv;
   HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
   if (two_phase) {
     st = prep(c, L, 1, A);
@@ -1186,7 +1217,7 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
   L.payoff_out = nullptr;
   bp.L = L;
   const int full = full_capacity(o, tb.max_dims, sizeof(T) == 8 ? 1 : 0);
-  if (memo.size() == 1) {
+  if (memo.size() == 1 && !o->history) {
     bp.spec = true;
     bp.tenv = memo.begin()->first;
     bp.tenv.push_back(0);

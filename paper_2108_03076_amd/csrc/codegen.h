@@ -27,7 +27,7 @@ std::string generate_payoff(const Program& P, const Grid* G, bool fixed);
 // iteration written out), capped at cap; kernels for one template
 // environment are generated only up to kMaxUnrolled.
 int64_t unrolled_size(const Program& P, const Grid& G, int i, int64_t cap);
-constexpr int64_t kMaxUnrolled = 4000;
+constexpr int64_t kMaxUnrolled = 1024;
 
 // Compiled kernels of one payoff, keyed by (device, precision, rng, assets,
 // memory source, paths per lane, whole-path capacity, single instrument,

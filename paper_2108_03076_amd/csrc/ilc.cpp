@@ -534,7 +534,7 @@ struct Walk {
 };
 }  // namespace
 
-int plan(const Program& p, const int32_t* tenv, Grid& g, std::string& err) {
+int plan(const Program& p, const int32_t* tenv, Grid& g, std::string& err, int32_t sim_from) {
   const size_t nv = p.tvars.size();
   for (size_t v = 0; v < nv; ++v)
     if (tenv[v] < 0) { err = "template variable '" + p.tvars[v] + "' is negative"; return PMC_E_TENV; }
@@ -560,7 +560,8 @@ int plan(const Program& p, const int32_t* tenv, Grid& g, std::string& err) {
   w.go(p.root, 0, 0);
   g.days.clear();
   g.daymap.assign((size_t)g.horizon + 1, -1);
-  for (int32_t d = 1; d <= g.horizon; ++d)
+  g.sim_from = std::max<int32_t>(0, sim_from);
+  for (int32_t d = g.sim_from + 1; d <= g.horizon; ++d)
     if (mark[d]) {
       g.daymap[d] = (int32_t)g.days.size();
       g.days.push_back(d);
@@ -589,7 +590,7 @@ int64_t fused_generation_cost(const Program& p, const Grid& g, int n_assets, int
       case OP_HALT: return generated;
       case OP_MODEL: {
         int64_t day = g.tt[in.imm] + t0;
-        if (day <= 0 || day > g.horizon) break;
+        if (day <= g.sim_from || day > g.horizon) break;
         int64_t s = g.daymap[day];
         if (s < 0) break;
         if (base >= 0 && s >= base && s < base + ws) break;

@@ -53,11 +53,14 @@ int cut_payoff(const Program& in, Program& out, std::string& err);
 // Per-template-environment plan: folded time table and simulated grid.
 struct Grid {
   std::vector<int32_t> tt;      // value of every time-table entry
-  std::vector<int32_t> days;    // simulated days (sorted, > 0)
+  std::vector<int32_t> days;    // simulated days (sorted, > sim_from)
   std::vector<int32_t> daymap;  // day 0..horizon -> slot or -1
   int32_t horizon = 0;
+  int32_t sim_from = 0;         // last history day: the simulation starts from it
 };
-int plan(const Program& p, const int32_t* tenv, Grid& g, std::string& err);
+// sim_from: the last day of a given price history (days up to it are not
+// simulated); 0 without one.
+int plan(const Program& p, const int32_t* tenv, Grid& g, std::string& err, int32_t sim_from = 0);
 
 // Estimated number of generated slots per path when the fused interpreter
 // serves the expression's reads through its kWindow-entry window (restarting

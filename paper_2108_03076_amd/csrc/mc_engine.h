@@ -402,6 +402,13 @@ __device__ __forceinline__ bool outside(int slot, int base, int ws) {
   return (uint32_t)(slot - base) >= (uint32_t)ws;
 }
 
+// Price of asset a on a history day: entry day - first of its row of the
+// history table, clamped to the row (flat before the first day).
+template <typename T>
+__device__ __forceinline__ T hist_value(kptr<T> h, int first, int n, int a, int day) {
+  return h[a * n + min(max(day - first, 0), n - 1)];
+}
+
 // Generates the path of one lane slot by slot into the window.  CAP = 0:
 // a window of kWindow values that slides forward and is regenerated from the
 // spot on a backward read (paths of any length).  CAP > 0 (a power of two,
@@ -429,7 +436,8 @@ struct GenSource {
   lptr<uint32_t> lo;         // LDS table of low-bit XORs, at this lane's Gray bits
   bool use_lo;
   kptr<T> slotc;
-  kptr<T> spotp;
+  kptr<T> histp;
+  int hist_first, n_hist;
   Model<T, A> M;
 
   __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p, lptr<uint32_t> lo_tab,
@@ -450,7 +458,8 @@ struct GenSource {
     }
     M.load(g, d, l_own, own);
     slotc = K(g.rtab) + d.slot_off;
-    spotp = K(g.rtab) + d.model_off + 2 * A;
+    histp = K(g.rtab) + d.hist_off;
+    hist_first = d.hist_first; n_hist = d.n_hist;
     base = kNoWindow; next_slot = 0; blk = 0xFFFFFFFFu;
 #pragma unroll
     for (int a = 0; a < A; ++a) x[a] = T(0);
@@ -611,7 +620,7 @@ struct GenSource {
       return win[i];
     }
   }
-  __device__ __forceinline__ T spot(int a) const { return spotp[a]; }
+  __device__ __forceinline__ T hist(int a, int day) const { return hist_value(histp, hist_first, n_hist, a, day); }
 };
 
 // Sobol words of a wave's 64 points differ only in Gray-code bits 0..5 (bit 5
@@ -661,12 +670,14 @@ struct MemSource {
   int base, n_slots;
   uint32_t path, n_paths;
   const T* paths;
-  kptr<T> spotp;
+  kptr<T> histp;
+  int hist_first, n_hist;
 
   __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p) {
     path = p; n_paths = d.n_paths; n_slots = d.n_slots; base = kNoWindow;
     paths = g.paths;
-    spotp = K(g.rtab) + d.model_off + 2 * A;
+    histp = K(g.rtab) + d.hist_off;
+    hist_first = d.hist_first; n_hist = d.n_hist;
   }
   // Loads slots s .. s+WS-1 (clamped) with WS * A independent loads.
   __device__ __forceinline__ void refill(Win& win, int s) {
@@ -686,7 +697,7 @@ struct MemSource {
     const int i = uni((slot - base) * A + a) & (kWindow - 1);
     return win[i];
   }
-  __device__ __forceinline__ T spot(int a) const { return spotp[a]; }
+  __device__ __forceinline__ T hist(int a, int day) const { return hist_value(histp, hist_first, n_hist, a, day); }
 };
 
 // The same with P consecutive paths per lane (path a multiple of P, the path
@@ -709,14 +720,16 @@ struct MemSourceLds {
   uint32_t path, n_paths;
   const T* paths;
   lwptr<T> lw;               // this lane's entry 0; entry i at lw + i * stride
-  kptr<T> spotp;
+  kptr<T> histp;
+  int hist_first, n_hist;
 
   __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p, lwptr<T> lds) {
     path = p; n_paths = d.n_paths; n_slots = d.n_slots; base = kNoWindow;
     paths = g.paths;
     stride = (int)blockDim.x * P;
     lw = lds + threadIdx.x * P;
-    spotp = K(g.rtab) + d.model_off + 2 * A;
+    histp = K(g.rtab) + d.hist_off;
+    hist_first = d.hist_first; n_hist = d.n_hist;
   }
   // Slots s .. s+WS-1 (clamped to the last): one 64-bit row offset, then
   // the others by adding the per-slot row stride (a window inside the path
@@ -756,32 +769,33 @@ struct MemSourceLds {
     for (int e = 0; e < P; ++e) r.v[e] = lw[i * stride + e];
     return r;
   }
-  __device__ __forceinline__ V spot(int a) const { return V(spotp[a]); }
+  __device__ __forceinline__ V hist(int a, int day) const { return V(hist_value(histp, hist_first, n_hist, a, day)); }
 };
 
-// An observable of a model asset on a day: the spot for day <= 0 (flat
-// history), else the simulated price of the day's slot.
-// The grid is given by its first day when dense (else 0: the day map dm),
-// its slot count and its horizon.
-// (A dense grid starts on a day >= 1, so its slot test also covers day <= 0.)
+// An observable of a model asset on a day: history for a day up to the
+// simulation's start sim_from (the given price history, flat before its
+// first day; without one, the spot), else the simulated price of the day's
+// slot.  The grid is given by its first day when dense (else 0: the day map
+// dm), its slot count and its horizon.  (A dense grid starts after sim_from,
+// so its slot test also covers the history days.)
 template <class Src>
 __device__ __forceinline__ typename Src::V read_obs(Src& src, typename Src::Win& win, int dense_first,
-                                                    int n_slots, int horizon, kptr<int32_t> dm, int day,
-                                                    int asset) {
+                                                    int n_slots, int horizon, int sim_from, kptr<int32_t> dm,
+                                                    int day, int asset) {
   int s;
   if (dense_first > 0) {
     s = min(day - dense_first, n_slots - 1);
   } else {
-    if (day <= 0) return src.spot(asset);
+    if (day <= sim_from) return src.hist(asset, day);
     s = uni(dm[min(day, horizon)]);
   }
-  return s < 0 ? src.spot(asset) : src.read(win, s, asset);
+  return s < 0 ? src.hist(asset, day) : src.read(win, s, asset);
 }
 
 template <class Src>
 __device__ __forceinline__ typename Src::V read_obs(Src& src, typename Src::Win& win, const InstDesc& D,
                                                     kptr<int32_t> dm, int day, int asset) {
-  return read_obs(src, win, D.dense_first, D.n_slots, D.horizon, dm, day, asset);
+  return read_obs(src, win, D.dense_first, D.n_slots, D.horizon, D.sim_from, dm, day, asset);
 }
 
 // ------------------------------------------------------- interpreter ------

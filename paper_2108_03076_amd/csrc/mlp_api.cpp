@@ -52,6 +52,7 @@ struct pmc_mlp {
   // batch-sized work buffers
   int B = 0;
   Buf X, Xt, Z[3], H[3], Ht[3], Y, dZ4, dZ4t, dZ[3], dZt[3], part_loss, loss_acc, partial;
+  Buf px, py;   // surrogate pricing: the in-box points and their predictions
 };
 
 #define MLP_TRY(m, expr)                                                                           \
@@ -327,11 +328,12 @@ extern "C" int pmc_mlp_train_epoch(pmc_mlp* m, const float* x, const float* y, i
     const double frac = std::min(1.0, (double)m->step / (double)o->total_steps);
     const double lr = o->lr_min + 0.5 * (o->lr_max - o->lr_min) * (1.0 + std::cos(M_PI * frac));
     m->step++;
-    const double c1 = 1.0 - std::pow(o->beta1, (double)m->step);
-    const double c2 = 1.0 - std::pow(o->beta2, (double)m->step);
+    // the moving averages use the FP32 betas: so do their bias corrections
+    const float b1 = (float)o->beta1, b2 = (float)o->beta2;
+    const double c1 = 1.0 - std::pow((double)b1, (double)m->step);
+    const double c2 = 1.0 - std::pow((double)b2, (double)m->step);
     MLP_TRY(m, mlp_adam(m->master.as<float>(), m->m.as<float>(), m->v.as<float>(), m->grad.as<float>(),
-                        (int)m->n_params, (float)lr, (float)o->beta1, (float)o->beta2, (float)o->eps, (float)c1,
-                        (float)c2, s));
+                        (int)m->n_params, (float)lr, b1, b2, (float)o->eps, (float)c1, (float)c2, s));
     rc = pack_all(m);
     if (rc != PMC_OK) return rc;
   }
@@ -339,6 +341,89 @@ extern "C" int pmc_mlp_train_epoch(pmc_mlp* m, const float* x, const float* y, i
   MLP_TRY(m, hipMemcpyAsync(&acc, m->loss_acc.p, 8, hipMemcpyDeviceToHost, s));
   MLP_TRY(m, hipStreamSynchronize(s));
   if (mean_loss) *mean_loss = acc / (double)(steps * B);
+  return PMC_OK;
+}
+
+extern "C" int pmc_mlp_price(pmc_mlp* m, const double* x, int64_t n, const pmc_payoff* p, const pmc_batch* b,
+                             const pmc_gbm* model, const pmc_opts* o, double* price_out, double* std_err_out,
+                             int* route_out) {
+  if (!m || !x || n < 1 || !p || !b || !model || !o || !price_out) return PMC_E_ARG;
+  if (b->n_inst != n) return ctx_fail(m->ctx, PMC_E_ARG, "the batch must describe the n points, in order");
+  pmc_payoff_info info;
+  if (pmc_payoff_get_info(p, &info) != PMC_OK) return PMC_E_ARG;
+  const int D = m->n_in, A = info.n_assets, nt = info.n_tvars, np = info.n_params;
+  // route: inside the network's input box (every input within [lo, hi]) or not
+  std::vector<int64_t> in_box, out_box;
+  for (int64_t i = 0; i < n; ++i) {
+    bool inside = true;
+    for (int d = 0; d < D; ++d) {
+      const double v = x[i * D + d];
+      if (!(v >= m->lo[d] && v <= m->hi[d])) inside = false;   // NaN is outside
+    }
+    (inside ? in_box : out_box).push_back(i);
+  }
+  std::vector<double> price(n, 0.0), se(n, 0.0);
+  hipStream_t s = ctx_stream(m->ctx);
+  if (!in_box.empty()) {
+    const int64_t k = (int64_t)in_box.size();
+    std::vector<float> xs((size_t)k * D);
+    for (int64_t j = 0; j < k; ++j)
+      for (int d = 0; d < D; ++d) xs[(size_t)j * D + d] = (float)x[in_box[j] * D + d];
+    MLP_TRY(m, hipSetDevice(ctx_device(m->ctx)));
+    MLP_TRY(m, m->px.ensure(xs.size() * sizeof(float)));
+    MLP_TRY(m, m->py.ensure((size_t)k * sizeof(float)));
+    MLP_TRY(m, hipMemcpyAsync(m->px.p, xs.data(), xs.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    int rc = pmc_mlp_infer(m, m->px.as<float>(), m->py.as<float>(), k);
+    if (rc != PMC_OK) return rc;
+    std::vector<float> ys((size_t)k);
+    MLP_TRY(m, hipMemcpyAsync(ys.data(), m->py.p, (size_t)k * sizeof(float), hipMemcpyDeviceToHost, s));
+    MLP_TRY(m, hipStreamSynchronize(s));
+    for (int64_t j = 0; j < k; ++j) price[in_box[j]] = ys[j];
+  }
+  if (!out_box.empty()) {
+    // the out-of-box instances as one batch; each keeps its own stream id
+    const size_t k = out_box.size();
+    std::vector<int32_t> tenv(k * nt);
+    std::vector<double> params(k * np), spot, vol, corr;
+    std::vector<uint32_t> ids(k);
+    if (nt && !b->tenv) return ctx_fail(m->ctx, PMC_E_ARG, "null tenv");
+    if (np && !b->params) return ctx_fail(m->ctx, PMC_E_ARG, "null params");
+    if (b->per_instance_model && (!b->spot || !b->vol)) return ctx_fail(m->ctx, PMC_E_ARG, "null spot or vol");
+    for (size_t j = 0; j < k; ++j) {
+      const int64_t i = out_box[j];
+      for (int v = 0; v < nt; ++v) tenv[j * nt + v] = b->tenv[i * nt + v];
+      for (int q = 0; q < np; ++q) params[j * np + q] = b->params[i * np + q];
+      ids[j] = b->instance_ids ? b->instance_ids[i] : (uint32_t)i;
+      if (b->per_instance_model) {
+        spot.insert(spot.end(), b->spot + i * A, b->spot + (i + 1) * A);
+        vol.insert(vol.end(), b->vol + i * A, b->vol + (i + 1) * A);
+        if (b->corr) corr.insert(corr.end(), b->corr + i * A * A, b->corr + (i + 1) * A * A);
+      }
+    }
+    pmc_batch sub{};
+    sub.n_inst = (int)k;
+    sub.tenv = nt ? tenv.data() : nullptr;
+    sub.params = np ? params.data() : nullptr;
+    sub.per_instance_model = b->per_instance_model;
+    sub.spot = b->per_instance_model ? spot.data() : nullptr;
+    sub.vol = b->per_instance_model ? vol.data() : nullptr;
+    sub.corr = (b->per_instance_model && b->corr) ? corr.data() : nullptr;
+    sub.instance_ids = ids.data();
+    std::vector<pmc_result> res(k);
+    int rc = pmc_price_batch(m->ctx, p, &sub, model, o, res.data());
+    if (rc != PMC_OK) return rc;
+    for (size_t j = 0; j < k; ++j) {
+      price[out_box[j]] = res[j].price;
+      se[out_box[j]] = res[j].std_err;
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) price_out[i] = price[i];
+  if (std_err_out)
+    for (int64_t i = 0; i < n; ++i) std_err_out[i] = se[i];
+  if (route_out) {
+    for (int64_t i : in_box) route_out[i] = 0;
+    for (int64_t i : out_box) route_out[i] = 1;
+  }
   return PMC_OK;
 }
 

@@ -73,6 +73,12 @@ struct InstDesc {
   int32_t first_item;  // index of its first partial-sum slot
   int32_t dense_first; // > 0: the slots are the consecutive days dense_first ..
                        // dense_first + n_slots - 1 (no day map lookup needed)
+  int32_t sim_from;    // the day the simulation starts from: days up to it
+                       // are history, later days are simulated slots
+  int32_t hist_off;    // real table: history [A][n_hist] (days hist_first ..
+                       // hist_first + n_hist - 1; the spot alone if none given)
+  int32_t hist_first;  // day of the history's first entry
+  int32_t n_hist;      // history entries per asset (>= 1)
 };
 
 }  // namespace pmc

@@ -22,6 +22,8 @@ extern "C" int pmc_risk_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* 
   if (I < 1) return ctx_fail(c, PMC_E_ARG, "n_inst must be >= 1");
   if (b->per_instance_model ? (!b->spot || !b->vol) : (!m->spot || !m->vol))
     return ctx_fail(c, PMC_E_ARG, "model spot and vol are required");
+  if (o->history)   // the simulation would start from the history, not the bumped spots
+    return ctx_fail(c, PMC_E_UNSUPPORTED, "risk runs do not take a price history");
   const double rel = r->rel_spot_bump, k = r->abs_vol_bump;
   if (!(rel > 0.0 && rel < 1.0) || !(k > 0.0) || !std::isfinite(k))
     return ctx_fail(c, PMC_E_ARG, "bumps must satisfy 0 < rel_spot_bump < 1 and abs_vol_bump > 0");

@@ -63,6 +63,26 @@ def mc_prices(pay: Payoff, points, n_paths, *, rate, years_per_day, seed, first_
     return price, se, path_dates, gpu_ms
 
 
+def family_batch(points):
+    """The worst-of autocall instances of points [n][8]: template variable
+    N = n_obs - 1 and a per-point model (spots, vols, equicorrelation)."""
+    p = np.asarray(points, dtype=np.float64)
+    tenv = (np.rint(p[:, 7]).astype(np.int32) - 1).reshape(-1, 1)
+    return dict(tenv=tenv, params=np.zeros((p.shape[0], 0)), spot=p[:, 0:3], vol=p[:, 3:6],
+                corr=equicorr(p[:, 6]), per_instance_model=True)
+
+
+def price_with_fallback(sur: Surrogate, pay: Payoff, points, n_paths, *, rate, years_per_day, seed, first_id=0):
+    """Prices of points [n][8]: the surrogate inside its input box, the
+    batched Monte Carlo engine (n_paths Philox paths, point i on stream
+    first_id + i) outside it (pmc_mlp_price).  Returns (price, Monte Carlo
+    standard error or 0, route: 0 surrogate, 1 Monte Carlo)."""
+    p = np.asarray(points, dtype=np.float64)
+    ids = np.arange(first_id, first_id + p.shape[0], dtype=np.uint32)
+    return sur.price(p, pay, **family_batch(p), rate=rate, years_per_day=years_per_day, instance_ids=ids,
+                     n_paths=n_paths, rng="philox", seed=seed, precision="f32")
+
+
 def train(sur: Surrogate, x, y, *, epochs, batch=4096, lr_max=1e-3, lr_min=1e-5, log=None):
     """Trains on device tensors x [n][8] (float32) and y [n] (float32) with a
     cosine learning-rate schedule over all steps; returns per-epoch losses."""
@@ -100,4 +120,4 @@ def timed_infer(sur: Surrogate, x, reps=20):
     return (time.perf_counter() - t0) / reps * 1e3, y
 
 
-__all__ = ["box_bounds", "equicorr", "mc_prices", "train", "errors", "timed_infer", "Context", "Surrogate"]
+__all__ = ["box_bounds", "equicorr", "family_batch", "price_with_fallback", "mc_prices", "train", "errors", "timed_infer", "Context", "Surrogate"]
