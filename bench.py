@@ -359,8 +359,8 @@ def main():
     tenv = T.reshape(-1, 1)
     params = np.stack([K, B], 1)
     print("[bench] C4 autotune", file=sys.stderr, flush=True)
-    bl, ppt = P.autotune_batch(pay4, tenv, params, **kw4)
-    print(f"[bench] C4 headline at {bl}x{ppt}", file=sys.stderr, flush=True)
+    bl, ppt, lanes = P.autotune_batch(pay4, tenv, params, **kw4)
+    print(f"[bench] C4 headline at {bl}x{ppt}x{lanes}", file=sys.stderr, flush=True)
 
     def step():
         res = P.price_batch(pay4, tenv, params, **kw4)
@@ -389,7 +389,8 @@ def main():
                                "80-120, barrier 50-80% of spot), 2^16 Philox paths each, one persistent "
                                "graph-replayed launch, autotuned tile, FP32 paths, FP64 sums",
                    "instances": 1024, "paths_per_instance": c4.n_paths, "path_dates": pd4,
-                   "tile": f"{bl}x{ppt}", "rng": "philox", "mode": "fused"},
+                   "tile": f"{bl}x{ppt}x{lanes} (threads per block x rounds per thread x paths per lane)",
+                   "rng": "philox", "mode": "fused"},
         "device_ms_per_step": graph_ms,
         "engine": "compiled payoff (hipRTC), generic over template environments",
         # graph_ms: HIP events on the library's stream around one graph replay

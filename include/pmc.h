@@ -157,6 +157,15 @@ int pmc_payoff_get_info(const pmc_payoff* p, pmc_payoff_info* out);
 int pmc_payoff_grid(const pmc_payoff* p, const int32_t* tenv, int32_t* days_out, int max_days,
                     int* n_slots, int* horizon);
 
+/* Whether, for this template environment and a simulation starting on day
+ * sim_from (0, or the last day of a price history), the expression reads
+ * the simulated days in non-decreasing order (checked with every branch and
+ * loop iteration taken).  If so (*streams = 1), the compiled engine
+ * generates its Philox paths as a stream: each date once, holding only the
+ * newest prices, and may give each lane several paths.  Errors: PMC_E_TENV,
+ * PMC_E_HORIZON. */
+int pmc_payoff_streams(const pmc_payoff* p, const int32_t* tenv, int32_t sim_from, int* streams);
+
 /* Risk-neutral GBM with constant rate, no dividends.  Prices S_a start at
  * spot[a]; log-price increments between simulated days are
  * (rate - vol_a^2/2) dt + vol_a sqrt(dt) w_a, w = L z, L L^T = corr,
@@ -272,14 +281,18 @@ typedef struct pmc_batch {
 int pmc_price_batch(pmc_ctx* ctx, const pmc_payoff* p, const pmc_batch* batch,
                     const pmc_gbm* model, const pmc_opts* opts, pmc_result* out);
 
-/* Autotune the batched launch (threads per block, paths per thread) for this
- * payoff and batch by timing graph replays of every candidate; the choice is
- * kept in the context and, when cache_path is not NULL, appended to that text
- * file as a line "key block ppt" (key = device, payoff hash, batch shape) and
- * reused from it on later calls.  *block_out and *ppt_out receive it. */
+/* Autotune the batched launch for this payoff and batch by timing graph
+ * replays of every candidate tile: threads per block (64, 128, 256), rounds
+ * per thread (1, 2, 4) and paths per lane per round (1, or 2 where the batch
+ * streams its paths: compiled engine, Philox, every instance's expression
+ * reading its dates strictly forward).  The choice is kept in the context
+ * and, when cache_path is not NULL, appended to that text file as a line
+ * "key block ppt lanes" (key = device, payoff hash, batch shape) and reused
+ * from it on later calls (a line that is not a launchable tile is ignored).
+ * *block_out, *ppt_out and *lanes_out (each may be NULL) receive it. */
 int pmc_autotune_batch(pmc_ctx* ctx, const pmc_payoff* p, const pmc_batch* batch,
                        const pmc_gbm* model, const pmc_opts* opts, const char* cache_path,
-                       int* block_out, int* ppt_out);
+                       int* block_out, int* ppt_out, int* lanes_out);
 
 /* Bump-and-revalue risk over a batch (the risk runs of thousands of
  * pricings of one compiled contract that motivate the engine, end of Sec. 6.2).

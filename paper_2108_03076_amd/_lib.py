@@ -107,6 +107,7 @@ _sig = {
     "pmc_payoff_cut": (_i, [_vp, _vp, C.POINTER(_vp)]),
     "pmc_payoff_get_info": (_i, [_vp, C.POINTER(PayoffInfo)]),
     "pmc_payoff_grid": (_i, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _i, C.POINTER(_i), C.POINTER(_i)]),
+    "pmc_payoff_streams": (_i, [_vp, C.POINTER(C.c_int32), C.c_int32, C.POINTER(_i)]),
     "pmc_price": (_i, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(Gbm), C.POINTER(Opts),
                        C.POINTER(Result)]),
     "pmc_price_noalloc": (_i, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(Gbm),
@@ -115,7 +116,7 @@ _sig = {
     "pmc_risk_batch": (_i, [_vp, _vp, C.POINTER(Batch), C.POINTER(Gbm), C.POINTER(Opts), C.POINTER(RiskOpts),
                             C.POINTER(Greeks)]),
     "pmc_autotune_batch": (_i, [_vp, _vp, C.POINTER(Batch), C.POINTER(Gbm), C.POINTER(Opts), C.c_char_p,
-                                C.POINTER(_i), C.POINTER(_i)]),
+                                C.POINTER(_i), C.POINTER(_i), C.POINTER(_i)]),
     "pmc_gen_paths": (_i, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(Gbm), C.POINTER(Opts), _vp, _vp, _vp]),
     "pmc_eval_paths": (_i, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(Gbm),
                             C.POINTER(Opts), _vp, C.POINTER(Result)]),
@@ -261,6 +262,14 @@ class Payoff:
         buf = C.create_string_buffer(n.value + 1)
         self.ctx.check(lib.pmc_payoff_source(self.h, tp, buf, n.value + 1, C.byref(n)))
         return buf.value.decode()
+
+    def streams(self, tenv=(), sim_from=0):
+        """pmc_payoff_streams: whether the expression reads its dates in
+        non-decreasing order for this environment (paths can be streamed)."""
+        t, tp = _i32(tenv if len(tenv) else [0])
+        out = C.c_int()
+        self.ctx.check(lib.pmc_payoff_streams(self.h, tp, int(sim_from), C.byref(out)))
+        return bool(out.value)
 
     def grid(self, tenv=()):
         t, tp = _i32(tenv if len(tenv) else [0])
@@ -527,8 +536,8 @@ def autotune_batch(payoff: Payoff, tenv, params, *, spot, vol, corr=None, rate=0
     else:
         g, keep2 = make_model(spot, vol, corr, rate, years_per_day)
     o = make_opts(**opts)
-    bl, pp = C.c_int(), C.c_int()
+    bl, pp, ln = C.c_int(), C.c_int(), C.c_int()
     payoff.ctx.check(lib.pmc_autotune_batch(payoff.ctx.h, payoff.h, C.byref(b), C.byref(g), C.byref(o),
                                             cache_path.encode() if cache_path else None, C.byref(bl),
-                                            C.byref(pp)))
-    return bl.value, pp.value
+                                            C.byref(pp), C.byref(ln)))
+    return bl.value, pp.value, ln.value

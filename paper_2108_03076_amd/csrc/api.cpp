@@ -95,7 +95,8 @@ struct pmc_ctx {
   int n_cu = 0;
   std::string device_name;
   GraphCache graph;
-  std::map<std::string, std::pair<int, int>> tuned;  // batch shape -> (block, ppt)
+  struct Tile { int block, ppt, lanes; };
+  std::map<std::string, Tile> tuned;  // batch shape -> tile
   std::map<std::string, int> occupancy;   // kernel variant and block size -> resident blocks per CU
   // Bumped whenever the device tables change content: an upload that
   // rewrites the blob, new direction numbers, a rebuilt Sobol high table.
@@ -135,6 +136,9 @@ struct pmc_payoff {
   const uint64_t serial = next_payoff_serial();
   mutable JitCache jit;   // compiled-engine kernels, built on first use
   mutable std::map<std::vector<int32_t>, int64_t> fused_cost;   // per template environment
+  // per template environment (and start of the simulation): whether the
+  // expression's reads go strictly forward, so paths can be streamed
+  mutable std::map<std::vector<int32_t>, bool> streamable;
 };
 
 // Errors of calls made without a context (payoff loading may run before
@@ -306,6 +310,16 @@ extern "C" int pmc_payoff_grid(const pmc_payoff* p, const int32_t* tenv, int32_t
     if (max_days < (int)g.days.size()) return PMC_E_ARG;
     std::copy(g.days.begin(), g.days.end(), days);
   }
+  return PMC_OK;
+}
+
+extern "C" int pmc_payoff_streams(const pmc_payoff* p, const int32_t* tenv, int32_t sim_from, int* streams) {
+  if (!p || (!tenv && !p->prog.tvars.empty()) || !streams || sim_from < 0) return PMC_E_ARG;
+  Grid g;
+  std::string err;
+  const int st = plan(p->prog, tenv, g, err, sim_from);
+  if (st != PMC_OK) return st;
+  *streams = stream_reads(p->prog, g, int64_t(1) << 22) ? 1 : 0;
   return PMC_OK;
 }
 
@@ -688,7 +702,7 @@ int balanced_grid(int items, int cap) {
 // stride.
 int resolve_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec, bool mem, const McLaunch& L,
                    int grid, int block, int lanes, int64_t asset_dates, int full, const int32_t* tenv,
-                   EngineLaunch& e) {
+                   EngineLaunch& e, bool stream = false) {
   const int A = (int)p->prog.assets.size();
   const bool cap = !L.queue && asset_dates <= kShortItem;
   e = EngineLaunch{};
@@ -712,7 +726,7 @@ int resolve_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec,
   std::string err;
   const bool single = !L.queue && !L.order;
   const bool own = !mem && L.factor != 0;
-  int st = p->jit.get(p->prog, c->device, prec, o->rng, A, mem, &f, err, lanes, full, tenv, single, own);
+  int st = p->jit.get(p->prog, c->device, prec, o->rng, A, mem, &f, err, lanes, full, tenv, single, own, stream);
   if (st != PMC_OK) return fail(c, st, err);
   if (cap) {
     char kb[64];
@@ -743,9 +757,9 @@ int run_engine(pmc_ctx* c, const EngineLaunch& e, const McLaunch& L, hipEvent_t 
 
 int launch_engine(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, int prec, bool mem, const McLaunch& L,
                   int grid, int block, int lanes = 1, int64_t asset_dates = 0, int full = 0,
-                  const int32_t* tenv = nullptr) {
+                  const int32_t* tenv = nullptr, bool stream = false) {
   EngineLaunch e;
-  const int st = resolve_engine(c, p, o, prec, mem, L, grid, block, lanes, asset_dates, full, tenv, e);
+  const int st = resolve_engine(c, p, o, prec, mem, L, grid, block, lanes, asset_dates, full, tenv, e, stream);
   return st != PMC_OK ? st : run_engine(c, e, L);
 }
 
@@ -758,6 +772,29 @@ int full_capacity(const pmc_opts* o, int64_t values, int prec) {
   int cap = 1;
   while (cap < values) cap <<= 1;
   return cap;
+}
+
+// Whether the payoff's reads for this template environment (simulation
+// from day sim_from) never go back to an earlier slot, memoized per payoff:
+// its generated paths can then be streamed (compiled engine, Philox).
+bool streamable(const pmc_payoff* p, const int32_t* tenv, int32_t sim_from) {
+  const size_t nv = p->prog.tvars.size();
+  std::vector<int32_t> key(tenv, tenv + (tenv ? nv : 0));
+  key.push_back(sim_from);
+  auto it = p->streamable.find(key);
+  if (it != p->streamable.end()) return it->second;
+  Grid g;
+  std::string err;
+  const bool ok = (nv == 0 || tenv) && plan(p->prog, tenv, g, err, sim_from) == PMC_OK &&
+                  stream_reads(p->prog, g, int64_t(1) << 22);
+  p->streamable.emplace(key, ok);
+  return ok;
+}
+
+// A launch that can stream its paths: compiled engine, Philox words, no
+// whole-path window.
+bool stream_launch(const pmc_opts* o, int full) {
+  return o->engine != PMC_ENGINE_INTERPRETER && o->rng == PMC_RNG_PHILOX && full == 0;
 }
 
 int engine_used(const pmc_opts* o) {
@@ -867,9 +904,11 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   const int prec = sizeof(T) == 8 ? 1 : 0;
   const int full = full_capacity(o, (int64_t)n_slots * A, prec);
   int mode = o->mode;
+  const int32_t sim_from = o->history ? o->t_now : 0;
+  const bool stream = !eval_only && stream_launch(o, full) && streamable(p, tenv, sim_from);
   if (eval_only) {
     mode = PMC_MODE_TWO_PHASE;
-  } else if (mode == PMC_MODE_AUTO && full > 0) {
+  } else if (mode == PMC_MODE_AUTO && (full > 0 || stream)) {
     mode = PMC_MODE_FUSED;   // the whole path is generated once
   } else if (mode == PMC_MODE_AUTO) {
     // fused unless the window would regenerate much more than one path
@@ -951,7 +990,7 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
     L.factor = 1;
     L.status = status_dev(c, 1);
     EngineLaunch e;
-    st = resolve_engine(c, p, o, prec, false, L, (int)tiles, block, 1, (int64_t)n_slots * A, full, env, e);
+    st = resolve_engine(c, p, o, prec, false, L, (int)tiles, block, 1, (int64_t)n_slots * A, full, env, e, stream);
     if (st != PMC_OK) return st;
     if (keyed) {   // the next identical call can reuse all of this
       auto& pr = c->prepared;
@@ -1153,6 +1192,8 @@ namespace {
 struct BatchPlan {
   McLaunch L;
   int grid = 0, block = 256, ppt = 1, n_inst = 0, mode = PMC_MODE_FUSED, full = 0;
+  int lanes = 1;                // paths per lane (streamed paths only)
+  bool stream = false;          // paths generated as a stream
   bool spec = false;            // one template environment shared by all instances:
   std::vector<int32_t> tenv;   // that environment (and a trailing 0)
   std::vector<uint64_t> n_paths;
@@ -1165,7 +1206,7 @@ const int32_t* spec_tenv(const BatchPlan& bp) { return bp.spec ? bp.tenv.data() 
 
 template <typename T>
 int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc_gbm* m, const pmc_opts* o,
-                  int block, int ppt, BatchPlan& bp) {
+                  int block, int ppt, int lanes, BatchPlan& bp) {
   const Program& P = p->prog;
   const int A = (int)P.assets.size();
   const int I = b->n_inst;
@@ -1189,10 +1230,17 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
     st = build_instance<T>(c, P, *m, *o, in, i, tb, &memo);
     if (st != PMC_OK) return st;
   }
+  // Streamed paths if every template environment of the batch reads
+  // strictly forward (then `lanes` paths per lane, else one).
+  const int full = full_capacity(o, tb.max_dims, sizeof(T) == 8 ? 1 : 0);
+  bool stream = stream_launch(o, full);
+  for (auto it = memo.begin(); stream && it != memo.end(); ++it)
+    stream = streamable(p, it->first.data(), o->history ? o->t_now : 0);
+  const uint64_t N = o->n_paths;
+  if (!stream || N < (uint64_t)lanes) lanes = 1;
   // work items (instance, tile), instances with the most slots first; the
   // item list is implicit: item i is tile i % tiles of instance order[i / tiles]
-  const uint64_t N = o->n_paths;
-  const uint32_t tile_paths = (uint32_t)block * (uint32_t)ppt;
+  const uint32_t tile_paths = (uint32_t)block * (uint32_t)ppt * (uint32_t)lanes;
   const uint32_t tiles = (uint32_t)((N + tile_paths - 1) / tile_paths);
   const size_t n_work = (size_t)I * tiles;
   if (n_work > (1u << 26))
@@ -1216,7 +1264,8 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
   L.ppt = ppt;
   L.payoff_out = nullptr;
   bp.L = L;
-  const int full = full_capacity(o, tb.max_dims, sizeof(T) == 8 ? 1 : 0);
+  bp.lanes = lanes;
+  bp.stream = stream;
   if (memo.size() == 1 && !o->history) {
     bp.spec = true;
     bp.tenv = memo.begin()->first;
@@ -1228,7 +1277,8 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
   } else {   // the generated kernel's own register and LDS use
     hipFunction_t f = nullptr;
     std::string err;
-    st = p->jit.get(P, c->device, sizeof(T) == 8 ? 1 : 0, o->rng, A, false, &f, err, 1, full, spec_tenv(bp));
+    st = p->jit.get(P, c->device, sizeof(T) == 8 ? 1 : 0, o->rng, A, false, &f, err, lanes, full, spec_tenv(bp),
+                    false, false, stream);
     if (st != PMC_OK) return fail(c, st, err);
     occ = mc_occupancy_jit(f, block);
   }
@@ -1246,7 +1296,8 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
 int batch_enqueue(pmc_ctx* c, const pmc_payoff* p, const pmc_opts* o, const BatchPlan& bp, int prec, int A) {
   int st = prep(c, bp.L, bp.n_inst, A);
   if (st != PMC_OK) return st;
-  return launch_engine(c, p, o, prec, false, bp.L, bp.grid, bp.block, 1, 0, bp.full, spec_tenv(bp));
+  return launch_engine(c, p, o, prec, false, bp.L, bp.grid, bp.block, bp.lanes, 0, bp.full, spec_tenv(bp),
+                       bp.stream);
 }
 
 // Everything a captured batch graph bakes in: the kernel variant, the grid,
@@ -1259,6 +1310,7 @@ void batch_graph_key(std::vector<uint8_t>& k, const pmc_ctx* c, const pmc_payoff
   put(k, p->serial);   // never reused: a freed payoff's kernels are never replayed
   put(k, prec); put(k, o->rng); put(k, o->engine);
   put(k, bp.n_inst); put(k, bp.grid); put(k, bp.block); put(k, bp.ppt); put(k, bp.full); put(k, bp.spec);
+  put(k, bp.lanes); put(k, bp.stream);
   put(k, bp.tenv.size());
   if (!bp.tenv.empty()) put_bytes(k, bp.tenv.data(), bp.tenv.size() * sizeof(int32_t));
   put(k, L.code); put(k, L.consts); put(k, L.desc); put(k, L.itab); put(k, L.rtab); put(k, L.chol);
@@ -1289,7 +1341,8 @@ int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_op
     if (o->engine != PMC_ENGINE_INTERPRETER) {   // compile outside the capture
       hipFunction_t f = nullptr;
       std::string err;
-      int jst = p->jit.get(p->prog, c->device, prec, o->rng, A, false, &f, err, 1, bp.full, spec_tenv(bp));
+      int jst = p->jit.get(p->prog, c->device, prec, o->rng, A, false, &f, err, bp.lanes, bp.full, spec_tenv(bp),
+                           false, false, bp.stream);
       if (jst != PMC_OK) { c->stream = saved; if (own) (void)hipStreamDestroy(cap); return fail(c, jst, err); }
     }
     HIP_TRY(c, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
@@ -1314,8 +1367,12 @@ int batch_run(pmc_ctx* c, const pmc_payoff* p, const BatchPlan& bp, const pmc_op
 }
 
 // A batch tile the kernels can run: whole waves, at most the 256 threads the
-// kernels are compiled for, and 1 .. 1024 paths per thread.
-bool valid_tile(int block, int ppt) { return block >= 64 && block <= 256 && block % 64 == 0 && ppt >= 1 && ppt <= 1024; }
+// kernels are compiled for, 1 .. 1024 rounds per thread, and 1, 2 or 4
+// paths per lane per round.
+bool valid_tile(int block, int ppt, int lanes) {
+  return block >= 64 && block <= 256 && block % 64 == 0 && ppt >= 1 && ppt <= 1024 &&
+         (lanes == 1 || lanes == 2 || lanes == 4);
+}
 
 std::string tune_key(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc_opts* o) {
   std::ostringstream k;
@@ -1344,11 +1401,12 @@ extern "C" int pmc_price_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch*
   if (st != PMC_OK) return st;
   if (!out) return fail(c, PMC_E_ARG, "null out");
   HIP_TRY(c, hipSetDevice(c->device));
-  int block = o->block ? o->block : 256, ppt = 1;
+  int block = o->block ? o->block : 256, ppt = 1, lanes = 1;
   auto it = c->tuned.find(tune_key(c, p, b, o));
   if (it != c->tuned.end() && !o->block) {
-    block = it->second.first;
-    ppt = it->second.second;
+    block = it->second.block;
+    ppt = it->second.ppt;
+    lanes = it->second.lanes;
   } else {
     // untuned: enough paths per thread to keep the item count (and the
     // partial-sum buffer) below 2^22
@@ -1357,8 +1415,8 @@ extern "C" int pmc_price_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch*
       ppt *= 2;
   }
   BatchPlan bp;
-  st = o->precision == PMC_FP64 ? batch_prepare<double>(c, p, b, m, o, block, ppt, bp)
-                                : batch_prepare<float>(c, p, b, m, o, block, ppt, bp);
+  st = o->precision == PMC_FP64 ? batch_prepare<double>(c, p, b, m, o, block, ppt, lanes, bp)
+                                : batch_prepare<float>(c, p, b, m, o, block, ppt, lanes, bp);
   if (st != PMC_OK) return st;
   float ms = 0;
   st = batch_run(c, p, bp, o, &ms);
@@ -1370,49 +1428,63 @@ extern "C" int pmc_price_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch*
 }
 
 extern "C" int pmc_autotune_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc_gbm* m,
-                                  const pmc_opts* o, const char* cache_path, int* block_out, int* ppt_out) {
+                                  const pmc_opts* o, const char* cache_path, int* block_out, int* ppt_out,
+                                  int* lanes_out) {
   int st = check_batch(c, p, b, m, o);
   if (st != PMC_OK) return st;
   HIP_TRY(c, hipSetDevice(c->device));
   const std::string key = tune_key(c, p, b, o);
-  if (cache_path) {  // cache file: one "key block ppt" line per entry
+  auto report = [&](int bl, int pp, int ln) {
+    c->tuned[key] = {bl, pp, ln};
+    if (block_out) *block_out = bl;
+    if (ppt_out) *ppt_out = pp;
+    if (lanes_out) *lanes_out = ln;
+  };
+  if (cache_path) {  // cache file: one "key block ppt lanes" line per entry
     std::ifstream f(cache_path);
-    std::string k;
-    int bl, pp;
-    while (f >> k >> bl >> pp)
-      if (k == key && valid_tile(bl, pp)) {   // an entry that is not a launchable tile is ignored
-        c->tuned[key] = {bl, pp};
-        if (block_out) *block_out = bl;
-        if (ppt_out) *ppt_out = pp;
+    std::string line;
+    while (std::getline(f, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      int bl = 0, pp = 0, ln = 0;
+      if (!(ls >> k >> bl >> pp >> ln)) continue;
+      if (k == key && valid_tile(bl, pp, ln)) {   // an entry that is not a launchable tile is ignored
+        report(bl, pp, ln);
         return PMC_OK;
       }
+    }
   }
+  // Candidates: threads per block x rounds per thread x paths per lane (more
+  // than one only where the batch streams its paths).  A candidate whose
+  // paths per lane the batch cannot use is the one-path tile, timed already.
   const int blocks[] = {64, 128, 256};
   const int ppts[] = {1, 2, 4};
+  const int lanes_c[] = {1, 2};
   float best = 1e30f;
-  int bb = 256, bpp = 1;
-  for (int bl : blocks)
-    for (int pp : ppts) {
-      if ((uint64_t)b->n_inst * ((o->n_paths + (uint64_t)bl * pp - 1) / ((uint64_t)bl * pp)) > (1ull << 24)) continue;
-      BatchPlan bp;
-      st = o->precision == PMC_FP64 ? batch_prepare<double>(c, p, b, m, o, bl, pp, bp)
-                                    : batch_prepare<float>(c, p, b, m, o, bl, pp, bp);
-      if (st != PMC_OK) return st;
-      float t = 1e30f;
-      for (int rep = 0; rep < 3; ++rep) {
-        float ms = 0;
-        st = batch_run(c, p, bp, o, &ms);
+  int bb = 256, bpp = 1, bln = 1;
+  for (int ln : lanes_c)
+    for (int bl : blocks)
+      for (int pp : ppts) {
+        const uint64_t tile = (uint64_t)bl * pp * ln;
+        if ((uint64_t)b->n_inst * ((o->n_paths + tile - 1) / tile) > (1ull << 24)) continue;
+        BatchPlan bp;
+        st = o->precision == PMC_FP64 ? batch_prepare<double>(c, p, b, m, o, bl, pp, ln, bp)
+                                      : batch_prepare<float>(c, p, b, m, o, bl, pp, ln, bp);
         if (st != PMC_OK) return st;
-        if (rep > 0) t = std::min(t, ms);   // first replay includes instantiation effects
+        if (bp.lanes != ln) continue;
+        float t = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          float ms = 0;
+          st = batch_run(c, p, bp, o, &ms);
+          if (st != PMC_OK) return st;
+          if (rep > 0) t = std::min(t, ms);   // first replay includes instantiation effects
+        }
+        if (t < best) { best = t; bb = bl; bpp = pp; bln = ln; }
       }
-      if (t < best) { best = t; bb = bl; bpp = pp; }
-    }
-  c->tuned[key] = {bb, bpp};
+  report(bb, bpp, bln);
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
-    f << key << ' ' << bb << ' ' << bpp << '\n';
+    f << key << ' ' << bb << ' ' << bpp << ' ' << bln << '\n';
   }
-  if (block_out) *block_out = bb;
-  if (ppt_out) *ppt_out = bpp;
   return PMC_OK;
 }

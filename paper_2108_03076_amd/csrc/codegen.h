@@ -36,8 +36,10 @@ class JitCache {
  public:
   ~JitCache();
   // Returns the kernel for the variant, compiling it on first use.
-  // lanes > 1 (paths per lane) is for the memory source only; full > 0 (a
-  // power of two, at most 32 values) holds each generated path whole; tenv:
+  // lanes > 1 (paths per lane) is for the memory source and for streamed
+  // paths; full > 0 (a power of two, at most 32 values) holds each generated
+  // path whole; stream: Philox paths generated as a stream (expressions
+  // whose reads never go back to an earlier slot); tenv:
   // the one template environment every instance of the launch has, for a
   // kernel generated for it; null for the generic kernel.  single: the
   // launch prices one instrument without a work queue or instance order,
@@ -46,17 +48,18 @@ class JitCache {
   // the kernel leaves out the prepared-factor branch.
   int get(const Program& P, int device, int precision, int rng, int n_assets, bool from_memory,
           hipFunction_t* out, std::string& err, int lanes = 1, int full = 0, const int32_t* tenv = nullptr,
-          bool single = false, bool own = false);
+          bool single = false, bool own = false, bool stream = false);
  private:
   // The cache key of a variant; g and spec receive the grid and whether the
   // kernel is generated for that one template environment.
   static std::string variant_key(const Program& P, int device, int precision, int rng, int n_assets, bool mem,
-                                 int lanes, int full, const int32_t* tenv, bool single, bool own, Grid& g,
-                                 bool& spec);
+                                 int lanes, int full, const int32_t* tenv, bool single, bool own, bool stream,
+                                 Grid& g, bool& spec);
   // hipRTC compile and module load of one variant; waves > 0 asks for that
   // many waves per SIMD.
   int compile(const std::string& src, int precision, int rng, int n_assets, bool mem, int lanes, int full,
-              bool single, bool own, int waves, hipModule_t* mod, hipFunction_t* fn, std::string& err);
+              bool single, bool own, bool stream, int waves, hipModule_t* mod, hipFunction_t* fn,
+              std::string& err);
   std::mutex mu_;
   std::map<std::string, std::pair<hipModule_t, hipFunction_t>> k_;
   std::string src_;  // generic generated payoff source (built once)

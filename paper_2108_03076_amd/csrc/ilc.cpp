@@ -569,6 +569,59 @@ int plan(const Program& p, const int32_t* tenv, Grid& g, std::string& err, int32
   return PMC_OK;
 }
 
+// ------------------------------------------------------- streamed reads --
+namespace {
+struct StreamWalk {
+  const Program& P;
+  const Grid& g;
+  int64_t budget;
+  int64_t last = -1;
+  bool ok = true;
+  bool dense = false;
+  // the slot a day reads (-1: history), as the engine maps it
+  int64_t slot_of(int64_t day) const {
+    if (day <= g.sim_from) return -1;
+    if (dense) return std::min<int64_t>(day - g.days.front(), (int64_t)g.days.size() - 1);
+    const int64_t s = g.daymap[(size_t)std::min<int64_t>(day, g.horizon)];
+    return s;
+  }
+  void go(int i, int64_t t0) {
+    if (!ok) return;
+    if (--budget < 0) { ok = false; return; }
+    const Node& n = P.nodes[i];
+    switch (n.kind) {
+      case Node::MODEL: {
+        const int64_t s = slot_of(g.tt[n.tt] + t0);
+        if (s < 0) break;
+        if (s < last) { ok = false; return; }
+        last = s;
+        break;
+      }
+      case Node::UN: go(n.kid[0], t0); break;
+      case Node::BIN: go(n.kid[0], t0); go(n.kid[1], t0); break;
+      case Node::IF: go(n.kid[0], t0); go(n.kid[1], t0); go(n.kid[2], t0); break;
+      case Node::LOOPIF: {
+        const int64_t count = g.tt[n.tt];
+        for (int64_t k = 0; k <= count && ok; ++k) {
+          go(n.kid[0], t0 + k);
+          go(n.kid[1], t0 + k);
+          if (k == count) go(n.kid[2], t0 + k);
+        }
+        break;
+      }
+      default: break;
+    }
+  }
+};
+}  // namespace
+
+bool stream_reads(const Program& p, const Grid& g, int64_t max_visits) {
+  StreamWalk w{p, g, max_visits};
+  w.dense = !g.days.empty() && g.days.back() - g.days.front() + 1 == (int32_t)g.days.size();
+  w.go(p.root, 0);
+  return w.ok;
+}
+
 // ------------------------------------------------- fused window cost model --
 int64_t fused_generation_cost(const Program& p, const Grid& g, int n_assets, int64_t max_events) {
   // Replays the bytecode's uniform control flow with every branch and every

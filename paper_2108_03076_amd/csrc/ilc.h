@@ -62,6 +62,13 @@ struct Grid {
 // simulated); 0 without one.
 int plan(const Program& p, const int32_t* tenv, Grid& g, std::string& err, int32_t sim_from = 0);
 
+// True if, evaluated with every branch taken and every loop iteration run
+// (in the order the compiled payoff evaluates its nodes), the expression
+// reads the simulated slots in non-decreasing order: then a path can be
+// generated as a stream, each slot once and only the newest one held.  False
+// also when the walk would exceed max_visits node visits.
+bool stream_reads(const Program& p, const Grid& g, int64_t max_visits);
+
 // Estimated number of generated slots per path when the fused interpreter
 // serves the expression's reads through its kWindow-entry window (restarting
 // generation on a backward read), assuming every branch and iteration runs.

@@ -623,6 +623,110 @@ struct GenSource {
   __device__ __forceinline__ T hist(int a, int day) const { return hist_value(histp, hist_first, n_hist, a, day); }
 };
 
+// Philox paths generated as a stream, for expressions whose reads never go
+// back to an earlier slot (the host checks every instance's reads; the
+// sliding window serves the others): each slot is generated once, when it
+// is first read, and only the newest slot's prices are held, so there is no
+// window to fill or index.  The words of a path are consumed in order, four
+// per Philox block, from a buffer that shifts down by one word per use.
+// P paths per lane (P >= 1) share the wave-uniform work of every read and of
+// the payoff's control flow (P = 2 halves the scalar instructions per
+// path-date).  Each path's words, normals, steps and prices are those of
+// GenSource, bit for bit.
+template <typename T, int A, int P>
+struct GenStream {
+  using V = VecT<T, P>;
+  using Mask = MaskT<P>;
+  static constexpr int kWin = 1;
+  using Win = char[1];
+  T x[P][A];
+  T cur[P][A];     // prices of slot `last`
+  int last;        // newest generated slot (uniform), -1 before the first
+  int left;        // words left in the buffer (uniform)
+  uint32_t next_blk;
+  uint32_t b0[P], b1[P], b2[P], b3[P];
+  uint32_t path, k0, k1, inst;
+  kptr<T> slotc;
+  kptr<T> histp;
+  int hist_first, n_hist;
+  Model<T, A> M;
+
+  __device__ __forceinline__ void restart() {
+#pragma unroll
+    for (int e = 0; e < P; ++e)
+#pragma unroll
+      for (int a = 0; a < A; ++a) x[e][a] = T(0);
+    last = -1; left = 0; next_blk = 0;
+  }
+  __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p, const T* l_own, bool own) {
+    path = p;
+    k0 = g.k0; k1 = g.k1; inst = d.instance;
+    M.load(g, d, l_own, own);
+    slotc = K(g.rtab) + d.slot_off;
+    histp = K(g.rtab) + d.hist_off;
+    hist_first = d.hist_first; n_hist = d.n_hist;
+    restart();
+  }
+  // the next word of each path
+  __device__ __forceinline__ void next_word(uint32_t (&out)[P]) {
+    if (left == 0) {
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        uint32_t o[4];
+        philox4x32_10(path + (uint32_t)e, next_blk, inst, 0u, k0, k1, o);
+        b0[e] = o[0]; b1[e] = o[1]; b2[e] = o[2]; b3[e] = o[3];
+      }
+      ++next_blk;
+      left = 4;
+    }
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      out[e] = b0[e];
+      b0[e] = b1[e]; b1[e] = b2[e]; b2[e] = b3[e];
+    }
+    --left;
+  }
+  // the next slot: GenSource::advance per path, then its prices
+  __device__ __forceinline__ void step() {
+    ++last;
+    uint32_t xw[A][P];
+#pragma unroll
+    for (int a = 0; a < A; ++a) next_word(xw[a]);
+    const T dt = slotc[2 * last], sdt = slotc[2 * last + 1];
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      T zs[A];
+#pragma unroll
+      for (int a = 0; a < A; ++a) zs[a] = Num<T>::normal_word_scaled(xw[a][e], sdt);
+#pragma unroll
+      for (int a = 0; a < A; ++a) {
+        T xa = x[e][a] + M.dr[a] * dt;
+#pragma unroll
+        for (int k = 0; k <= a; ++k) xa = xa + M.C[a][k] * zs[k];
+        x[e][a] = xa;
+      }
+#pragma unroll
+      for (int a = 0; a < A; ++a) cur[e][a] = M.s0[a] * Num<T>::exps(x[e][a]);
+    }
+  }
+  __device__ __forceinline__ void prime(Win&) {}
+  __device__ __forceinline__ V read(Win&, int slot, int a) {
+    if (slot != last) {
+      if (slot < last) restart();   // never for a checked expression; kept correct
+      do { step(); } while (last < slot);
+    }
+    if constexpr (P == 1) {
+      return cur[0][a];
+    } else {
+      V r;
+#pragma unroll
+      for (int e = 0; e < P; ++e) r.v[e] = cur[e][a];
+      return r;
+    }
+  }
+  __device__ __forceinline__ V hist(int a, int day) const { return V(hist_value(histp, hist_first, n_hist, a, day)); }
+};
+
 // Sobol words of a wave's 64 points differ only in Gray-code bits 0..5 (bit 5
 // also takes bit 6 of the point index): entry [w][b] of the block's LDS table
 // is the XOR of dimension w's direction numbers selected by the bits of b, so
@@ -938,8 +1042,10 @@ struct Interp {
   }
 };
 
-// P > 1 (two-phase only): each lane evaluates P consecutive paths; a tile
-// is then P * blockDim paths.
+// P > 1 (stored or streamed paths): each lane evaluates P consecutive
+// paths; a tile is then P * blockDim paths.
+// STREAM: generated Philox paths as a stream (GenStream): for expressions
+// that never read back to an earlier slot.
 // FULL > 0: generated paths are held whole (GenSource's CAP; every
 // instance of the launch has n_slots * A <= FULL).
 // SINGLE: the launch prices one instrument in a fixed grid stride (no work
@@ -947,9 +1053,10 @@ struct Interp {
 // OWN: every launch of the kernel has each block factor its instrument's
 // matrix (Args::factor is 1), so the prepared-factor branch is compiled out.
 template <typename T, int RNG, int A, bool MEM, class Eval, int P = 1, int FULL = 0, bool SINGLE = false,
-          bool OWN = false>
+          bool OWN = false, bool STREAM = false>
 __device__ __forceinline__ void mc_body(const Args<T>& g) {
-  static_assert(P == 1 || MEM, "several paths per lane are for stored paths only");
+  static_assert(!STREAM || (RNG == 0 && !MEM && FULL == 0), "streamed paths: Philox, generated, no whole path");
+  static_assert(P == 1 || MEM || STREAM, "several generated paths per lane are streamed");
   static_assert(FULL == 0 || !MEM, "whole-path windows are for generated paths");
   // Wave priorities: the instruction arbiter favours older waves among equal
   // priorities, so a block that arrives a little later would have its set-up
@@ -1042,6 +1149,10 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
       } else if constexpr (MEM) {
         MemSource<T, A> src;
         src.init(g, D, p);
+        v = Eval::template run<T>(g, D, src, frames);
+      } else if constexpr (STREAM) {
+        GenStream<T, A, P> src;
+        src.init(g, D, p, l_own, own);
         v = Eval::template run<T>(g, D, src, frames);
       } else {
         GenSource<T, RNG, A, FULL> src;

@@ -23,7 +23,12 @@ hipcc = shutil.which("hipcc")
                                        ("C1", ("double", 0, 1, 0, 1, 1, 1, 1)),
                                        ("C3", ("float", 0, 1, 0, 1, 0, 1, 1)),
                                        # one instrument from stored paths (prepared factor)
-                                       ("C3", ("float", 0, 1, 1, 16, 0, 1, 0))])
+                                       ("C3", ("float", 0, 1, 1, 16, 0, 1, 0)),
+                                       # streamed paths: one or two per lane, batch or one instrument
+                                       ("C3", ("float", 0, 1, 0, 1, 0, 0, 0, 1)),
+                                       ("C3", ("float", 0, 1, 0, 2, 0, 0, 0, 1)),
+                                       ("C1", ("double", 0, 1, 0, 2, 0, 1, 1, 1)),
+                                       ("C2D", ("float", 0, 2, 0, 4, 0, 0, 0, 1))])
 def test_generated_payoff_compiles(tmp_path, name, defs):
     import paper_2108_03076_amd as P
     cfg = W.CONFIGS[name]
@@ -32,11 +37,11 @@ def test_generated_payoff_compiles(tmp_path, name, defs):
     assert "struct GenPayoff" in src and "pmc_jit_mc" in src
     f = tmp_path / "payoff.hip"
     f.write_text(src)
-    real, rng, a, mem, lanes, full, single, own = (defs + (0, 0))[:8]
+    real, rng, a, mem, lanes, full, single, own, stream = (defs + (0, 0, 0))[:9]
     cmd = [hipcc, "--offload-arch=gfx950", "-O1", "-std=c++17", "-include", "hip/hip_runtime.h", "-c", str(f),
            "-o", str(tmp_path / "payoff.o"), f"-DPMC_REAL={real}", f"-DPMC_RNG={rng}", f"-DPMC_A={a}",
            f"-DPMC_MEM={mem}", f"-DPMC_P={lanes}", f"-DPMC_FULL={full}", f"-DPMC_SINGLE={single}",
-           f"-DPMC_OWN={own}"]
+           f"-DPMC_OWN={own}", f"-DPMC_STREAM={stream}"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
 

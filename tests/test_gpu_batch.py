@@ -2,10 +2,11 @@
 kernel, Sec. 2 and Sec. 6.2) at the shape the benchmark times: the
 1024-instance down-and-out workload with 252..1260 daily dates.
 
-* Sample instances at 2^12 paths, at the tiles (threads per block x paths
-  per thread) 256 x 4 and 128 x 2 forced through the autotuner's cache
-  file, and at the autotuner's own choice: prices against the stored FP64
-  oracle prices on the same streams.
+* Sample instances at 2^12 paths, at the tiles (threads per block x rounds
+  per thread x paths per lane) 256 x 4 x 1, 128 x 2 x 1 and 128 x 2 x 2
+  (two streamed paths per lane) forced through the autotuner's cache file,
+  and at the autotuner's own choice: prices against the stored FP64 oracle
+  prices on the same streams.
 * Exact pins: a vanishing barrier gives the vanilla call on the same
   stream; a barrier at or above the spot knocks out on day 0 (price 0).
 * The full batch (1024 x 2^16 paths) at the tuned tile: six instances
@@ -42,8 +43,8 @@ def _sample():
 
 def _tune_key(cache):
     lines = [l.split() for l in cache.read_text().splitlines() if l.strip()]
-    assert len(lines) == 1 and len(lines[0]) == 3, lines
-    return lines[0][0], int(lines[0][1]), int(lines[0][2])
+    assert len(lines) == 1 and len(lines[0]) == 4, lines
+    return lines[0][0], int(lines[0][1]), int(lines[0][2]), int(lines[0][3])
 
 
 def _check_vs_oracle(res, inst, tag):
@@ -66,26 +67,28 @@ def test_sample_instances_at_forced_and_tuned_tiles(tmp_path):
     kw = dict(**model_kw(CFG), **opts_kw(CFG, n), instance_ids=ids)
     cache = tmp_path / "tune.txt"
     print("[batch] autotune with a cache file", flush=True)
-    bl, pp = P.autotune_batch(pay, T, KB, cache_path=str(cache), **kw)
-    key, fbl, fpp = _tune_key(cache)
-    assert (fbl, fpp) == (bl, pp) and bl in (64, 128, 256) and pp in (1, 2, 4)
+    bl, pp, ln = P.autotune_batch(pay, T, KB, cache_path=str(cache), **kw)
+    key, fbl, fpp, fln = _tune_key(cache)
+    assert (fbl, fpp, fln) == (bl, pp, ln) and bl in (64, 128, 256) and pp in (1, 2, 4) and ln in (1, 2)
     tuned = P.price_batch(pay, T, KB, **kw)
-    _check_vs_oracle(tuned, inst, f"tuned {bl}x{pp}")
+    _check_vs_oracle(tuned, inst, f"tuned {bl}x{pp}x{ln}")
     results = {}
-    for fbl, fpp in ((256, 4), (128, 2)):
-        cache.write_text(f"{key} {fbl} {fpp}\n")
-        assert P.autotune_batch(pay, T, KB, cache_path=str(cache), **kw) == (fbl, fpp)
-        print(f"[batch] forced tile {fbl}x{fpp}", flush=True)
+    for tile in ((256, 4, 1), (128, 2, 1), (128, 2, 2)):
+        cache.write_text(f"{key} {tile[0]} {tile[1]} {tile[2]}\n")
+        assert P.autotune_batch(pay, T, KB, cache_path=str(cache), **kw) == tile
+        print(f"[batch] forced tile {tile}", flush=True)
         res = P.price_batch(pay, T, KB, **kw)
-        _check_vs_oracle(res, inst, f"tile {fbl}x{fpp}")
-        results[(fbl, fpp)] = res
+        _check_vs_oracle(res, inst, f"tile {tile}")
+        results[tile] = res
     # the same paths whatever the tile: sums agree up to their order
-    for a, b in zip(results[(256, 4)], results[(128, 2)]):
-        assert a["sum"] == pytest.approx(b["sum"], rel=1e-12, abs=1e-9)
+    for t in ((128, 2, 1), (128, 2, 2)):
+        for a, b in zip(results[(256, 4, 1)], results[t]):
+            assert a["sum"] == pytest.approx(b["sum"], rel=1e-12, abs=1e-9), t
     # a cache entry that is not a launchable tile is ignored (tuned again)
-    cache.write_text(f"{key} 100 0\n")
-    bl2, pp2 = P.autotune_batch(pay, T, KB, cache_path=str(cache), **kw)
-    assert bl2 % 64 == 0 and 64 <= bl2 <= 256 and pp2 >= 1
+    for bad in ("100 0 1", "128 2 3"):
+        cache.write_text(f"{key} {bad}\n")
+        bl2, pp2, ln2 = P.autotune_batch(pay, T, KB, cache_path=str(cache), **kw)
+        assert bl2 % 64 == 0 and 64 <= bl2 <= 256 and pp2 >= 1 and ln2 in (1, 2)
 
 
 def test_sample_instances_equal_single_prices():
@@ -131,8 +134,8 @@ def test_full_batch_at_tuned_tile():
     tenv = T.reshape(-1, 1)
     pay = gpu_payoff(CFG)
     kw = dict(**model_kw(CFG), **opts_kw(CFG, n))
-    bl, pp = P.autotune_batch(pay, tenv, np.stack([K, B], 1), **kw)
-    print(f"[batch] full 1024 x 2^16 at {bl}x{pp}", flush=True)
+    bl, pp, ln = P.autotune_batch(pay, tenv, np.stack([K, B], 1), **kw)
+    print(f"[batch] full 1024 x 2^16 at {bl}x{pp}x{ln}", flush=True)
     do = P.price_batch(pay, tenv, np.stack([K, B], 1), **kw)
     van = P.price_batch(pay, tenv, np.stack([K, np.zeros_like(B)], 1), **kw)
     worst = 0.0

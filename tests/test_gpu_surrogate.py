@@ -240,17 +240,18 @@ def test_surrogate_price_routes_out_of_box_points_to_monte_carlo():
 
 
 def test_surrogate_meets_rms_bound_against_mc_judge():
-    """The learned surrogate at a reduced scale: trained on 2^15 Monte Carlo
-    labels (2^12 Philox paths each) of the worst-of autocall family, judged
-    by Monte Carlo at 2^16 paths (another seed) on 512 held-out points.  Its
-    RMS relative error must stay within the stated bound, and below that of
-    the plain method it learned from (Monte Carlo at the labels' 2^12 paths,
-    a third seed) on the same points."""
+    """The learned surrogate at a reduced scale: trained on 2^16 Monte Carlo
+    labels (2^12 Philox paths each) of the worst-of autocall family for 200
+    epochs, judged by Monte Carlo at 2^16 paths (another seed) on 512
+    held-out points.  Its RMS relative error must stay within 0.5 % (the
+    surrogate's error target, here including the judge's own 0.13 %), and
+    below that of the plain method it learned from (Monte Carlo at the
+    labels' 2^12 paths, a third seed) on the same points."""
     from paper_2108_03076_amd import surrogate as S
     cfg = W.C5
     pay = _c5_payoff()
     kw = dict(rate=cfg.rate, years_per_day=cfg.years_per_day)
-    xtr = W.c5_points(1 << 15, 42)
+    xtr = W.c5_points(1 << 16, 42)
     ytr, _, _, _ = S.mc_prices(pay, xtr, 1 << 12, seed=42, **kw)
     xte = W.c5_points(512, 43)
     yte, sete, _, _ = S.mc_prices(pay, xte, 1 << 16, seed=43, **kw)
@@ -258,7 +259,7 @@ def test_surrogate_meets_rms_bound_against_mc_judge():
     sur = _net(seed=9)
     xt = torch.tensor(xtr, dtype=torch.float32, device="cuda")
     yt = torch.tensor(ytr, dtype=torch.float32, device="cuda")
-    S.train(sur, xt, yt, epochs=40, batch=512, lr_max=2e-3, lr_min=1e-5)
+    S.train(sur, xt, yt, epochs=200, batch=1024, lr_max=3e-3, lr_min=1e-5)
     price, _, route = S.price_with_fallback(sur, pay, xte, 1 << 12, seed=44, **kw)
     assert not route.any()
     err = S.errors(price, yte)
@@ -266,5 +267,5 @@ def test_surrogate_meets_rms_bound_against_mc_judge():
     judge = float(np.median(sete / yte))
     print(f"[surrogate] rms {err['rms']:.4%} p99 {err['p99']:.4%} max {err['max']:.4%}; plain MC at 2^12 paths "
           f"rms {base['rms']:.4%}; judge relative SE {judge:.4%}", flush=True)
-    assert err["rms"] <= 0.02, err
+    assert err["rms"] <= 0.005, err
     assert err["rms"] < base["rms"], (err, base)

@@ -89,3 +89,27 @@ def test_cut_and_generated_source():
     src = c.source()
     assert "D.t_now" in src and "pmc_jit_mc" in src
     assert "D.t_now" not in p.source().split("struct GenPayoff")[1]
+
+
+def test_streamed_reads():
+    """Which expressions read their dates in non-decreasing order (their
+    paths can be generated as a stream): the down-and-out and the European
+    call do, at any maturity and after a history; the worst-of autocall's
+    maturity branch looks back three dates and does not, nor does a loop
+    that reads the day before its shift after its shift (one that reads it
+    first does: the shift's day is then the newest slot)."""
+    import paper_2108_03076_amd as P
+    for cfg, envs in ((W.C3, ([1260], [60], [0])), (W.C1, ([252],)), (W.C4, ([252], [1000]))):
+        pay = P.load_payoff(cfg.il, cfg.asset_labels, cfg.param_labels, cfg.tvars)
+        for env in envs:
+            assert pay.streams(env), (cfg.name, env)
+            assert pay.streams(env, sim_from=5), (cfg.name, env)
+    c2 = W.C2
+    pay = P.load_payoff(c2.il, c2.asset_labels, c2.param_labels, c2.tvars)
+    assert not pay.streams(c2.tenv)
+    fwd = P.load_payoff("(loopif (lt (model S (int -1)) (model S 0)) (payoff 0 X Y) (real 0.0) 30)", ["S"])
+    assert fwd.streams([])
+    back = P.load_payoff("(loopif (lt (model S 0) (model S (int -1))) (payoff 0 X Y) (real 0.0) 30)", ["S"])
+    assert not back.streams([])
+    # the same read after a history that covers it: no simulated slot is revisited
+    assert back.streams([], sim_from=40)
