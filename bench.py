@@ -426,6 +426,11 @@ def main():
 
     extra = {}
     line["hbm_copy_measured_GBs"] = hbm_copy_gbs()
+    # measured vector-ALU rates (pmc_probe_valu), beside the derived peak
+    probes = {name: ctx.probe_valu(k) / 1e12 for k, name in
+              enumerate(("fp32_fma", "int32_xor_add", "mad_u64_u32_add", "fp32_exp2_mul", "fp32_fma_with_xor"))}
+    line["valu_measured_T_lane_ops_per_s"] = probes
+    line["roofline"]["frac_of_measured_fp32_fma"] = achieved / probes["fp32_fma"]
     if want("C4sep"):
         # the same 1024 instruments as separate pmc_price calls
         print("[bench] C4 as 1024 separate calls", file=sys.stderr, flush=True)

@@ -339,6 +339,16 @@ int pmc_eval_paths(pmc_ctx* ctx, const pmc_payoff* p, const int32_t* tenv, const
  * Errors: PMC_E_NOT_PD (first failing matrix index in pmc_last_error). */
 int pmc_cholesky(pmc_ctx* ctx, const double* a, int n, int m, double* l_out);
 
+/* Peak-rate probe (diagnostic, for roofline figures): the vector-ALU lane
+ * operations per second this device sustains for one instruction class,
+ * from a kernel of independent dependency chains on 2048 blocks of 256
+ * threads (8 waves per SIMD on 256 CUs) with no memory traffic in its timed
+ * loop.  kind 0: FP32 fused multiply-add (v_fma_f32); 1: 32-bit xor and add;
+ * 2: 32 x 32 -> 64-bit multiply-add (v_mad_u64_u32) and a 32-bit add;
+ * 3: FP32 exp2 (v_exp_f32) and a multiply; 4: independent FP32 FMA and
+ * 32-bit xor chains interleaved.  Allocates and frees 32 bytes. */
+int pmc_probe_valu(pmc_ctx* ctx, int kind, double* lane_ops_per_s);
+
 /* ---- learned surrogate: MLP 8 -> W -> W -> W -> 1 (GELU), BF16 weights and
  * activations with FP32 accumulation on MFMA; FP32 master weights and Adam.
  * Inputs are min-max scaled to [-1, 1] by the library (lo/hi per input);

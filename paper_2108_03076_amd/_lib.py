@@ -120,6 +120,7 @@ _sig = {
     "pmc_gen_paths": (_i, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(Gbm), C.POINTER(Opts), _vp, _vp, _vp]),
     "pmc_eval_paths": (_i, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(Gbm),
                             C.POINTER(Opts), _vp, C.POINTER(Result)]),
+    "pmc_probe_valu": (_i, [_vp, _i, C.POINTER(C.c_double)]),
     "pmc_cholesky": (_i, [_vp, C.POINTER(C.c_double), _i, _i, C.POINTER(C.c_double)]),
     "pmc_mlp_create": (_i, [_vp, _i, _i, _u64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
                             C.POINTER(_vp)]),
@@ -197,6 +198,14 @@ class Context:
 
     def load(self, il, assets, params=(), tvars=()):
         return Payoff(self, il, assets, params, tvars)
+
+    def probe_valu(self, kind):
+        """Sustained vector-ALU lane operations per second for one instruction
+        class (pmc_probe_valu): 0 FP32 FMA, 1 int32 xor+add, 2 v_mad_u64_u32
+        + add, 3 FP32 exp2 + multiply, 4 FP32 FMA and int32 xor interleaved."""
+        out = C.c_double()
+        self.check(lib.pmc_probe_valu(self.h, int(kind), C.byref(out)))
+        return out.value
 
     def cholesky(self, mats):
         m = np.ascontiguousarray(np.asarray(mats, dtype=np.float64))

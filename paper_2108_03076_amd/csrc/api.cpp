@@ -76,6 +76,20 @@ struct GraphCache {
   ~GraphCache() { if (exec) (void)hipGraphExecDestroy(exec); }
 };
 
+// A batched launch, ready to run: launch arguments, grid and tile, and what
+// the results need.
+struct BatchPlan {
+  McLaunch L;
+  int grid = 0, block = 256, ppt = 1, n_inst = 0, mode = PMC_MODE_FUSED, full = 0;
+  int lanes = 1;                // paths per lane (streamed paths only)
+  bool stream = false;          // paths generated as a stream
+  bool spec = false;            // one template environment shared by all instances:
+  std::vector<int32_t> tenv;   // that environment (and a trailing 0)
+  std::vector<uint64_t> n_paths;
+  std::vector<int> n_slots;
+  int64_t path_dates = 0;
+};
+
 }  // namespace
 
 struct pmc_ctx {
@@ -116,6 +130,16 @@ struct pmc_ctx {
     int n_slots = 0;
     int engine = 0;
   } prepared;
+  // The same for the last batch: a call whose inputs and tile are
+  // byte-identical, with the tables and buffers unchanged since, replays its
+  // graph without rebuilding the instance tables.
+  struct PreparedBatch {
+    bool valid = false;
+    std::vector<uint8_t> key;
+    uint64_t gen = 0;
+    const void* bufs[8] = {};
+    BatchPlan bp;
+  } prepared_batch;
   std::vector<uint8_t> key_buf;   // scratch for a call's key
   // The device address of the allocation-free call's scratch on this
   // device (null, with the reason, if the lookup failed).
@@ -844,6 +868,43 @@ bool call_key(std::vector<uint8_t>& k, const pmc_payoff* p, int real_size, const
   return true;
 }
 
+// Serializes everything a batched pricing depends on, with its tile; false
+// if an input pointer is missing (the call then takes the checked path).
+bool batch_call_key(std::vector<uint8_t>& k, const pmc_payoff* p, const pmc_batch* b, const pmc_gbm* m,
+                    const pmc_opts* o, int block, int ppt, int lanes) {
+  const Program& P = p->prog;
+  const size_t A = P.assets.size(), I = (size_t)b->n_inst, nv = P.tvars.size(), nq = P.params.size();
+  const bool per = b->per_instance_model != 0;
+  const double* sp = per ? b->spot : m->spot;
+  const double* vo = per ? b->vol : m->vol;
+  const double* co = per ? b->corr : m->corr;
+  if ((nv && !b->tenv) || (nq && !b->params) || !sp || !vo || !o->party_from || !o->party_to) return false;
+  const size_t rows = per ? I : 1;
+  k.clear();
+  put(k, p->serial);
+  put(k, block); put(k, ppt); put(k, lanes); put(k, b->n_inst);
+  if (nv) put_bytes(k, b->tenv, I * nv * sizeof(int32_t));
+  if (nq) put_bytes(k, b->params, I * nq * sizeof(double));
+  put(k, (uint8_t)per);
+  put_bytes(k, sp, rows * A * sizeof(double));
+  put_bytes(k, vo, rows * A * sizeof(double));
+  put(k, (uint8_t)(co != nullptr));
+  if (co) put_bytes(k, co, rows * A * A * sizeof(double));
+  put(k, (uint8_t)(b->instance_ids != nullptr));
+  if (b->instance_ids) put_bytes(k, b->instance_ids, I * sizeof(uint32_t));
+  put(k, m->rate); put(k, m->years_per_day);
+  put(k, o->n_paths); put(k, o->rng); put(k, o->seed); put(k, o->instance); put(k, o->precision);
+  put(k, o->t_now); put(k, o->mode); put(k, o->block); put(k, o->engine);
+  put_bytes(k, o->party_from, std::strlen(o->party_from) + 1);
+  put_bytes(k, o->party_to, std::strlen(o->party_to) + 1);
+  put(k, (uint8_t)(o->history != nullptr));
+  if (o->history) {
+    put(k, o->history_len);
+    put_bytes(k, o->history, A * (size_t)o->history_len * sizeof(double));
+  }
+  return true;
+}
+
 // The device buffers a prepared launch points into (reallocation of any of
 // them invalidates it).
 void buffer_snapshot(const pmc_ctx* c, const void* (&b)[8]) {
@@ -1189,18 +1250,6 @@ extern "C" int pmc_gen_paths(pmc_ctx* c, const pmc_payoff* p, const int32_t* ten
 // ------------------------------------------------------------ batched ------
 namespace {
 
-struct BatchPlan {
-  McLaunch L;
-  int grid = 0, block = 256, ppt = 1, n_inst = 0, mode = PMC_MODE_FUSED, full = 0;
-  int lanes = 1;                // paths per lane (streamed paths only)
-  bool stream = false;          // paths generated as a stream
-  bool spec = false;            // one template environment shared by all instances:
-  std::vector<int32_t> tenv;   // that environment (and a trailing 0)
-  std::vector<uint64_t> n_paths;
-  std::vector<int> n_slots;
-  int64_t path_dates = 0;
-};
-
 // The template environment a batch's kernel is generated for, or null.
 const int32_t* spec_tenv(const BatchPlan& bp) { return bp.spec ? bp.tenv.data() : nullptr; }
 
@@ -1414,10 +1463,31 @@ extern "C" int pmc_price_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch*
                              (1ull << 22))
       ppt *= 2;
   }
-  BatchPlan bp;
-  st = o->precision == PMC_FP64 ? batch_prepare<double>(c, p, b, m, o, block, ppt, lanes, bp)
-                                : batch_prepare<float>(c, p, b, m, o, block, ppt, lanes, bp);
-  if (st != PMC_OK) return st;
+  // A call identical to the previous batch, with the tables and buffers
+  // untouched since: its plan (and graph) serve again; the kernels all run.
+  auto& pb = c->prepared_batch;
+  const bool keyed = batch_call_key(c->key_buf, p, b, m, o, block, ppt, lanes);
+  bool hit = keyed && pb.valid && pb.gen == c->table_gen && pb.key == c->key_buf;
+  if (hit) {
+    const void* bufs[8];
+    buffer_snapshot(c, bufs);
+    hit = std::memcmp(bufs, pb.bufs, sizeof bufs) == 0;
+  }
+  if (!hit) {
+    pb.valid = false;
+    BatchPlan fresh;
+    st = o->precision == PMC_FP64 ? batch_prepare<double>(c, p, b, m, o, block, ppt, lanes, fresh)
+                                  : batch_prepare<float>(c, p, b, m, o, block, ppt, lanes, fresh);
+    if (st != PMC_OK) return st;
+    pb.bp = std::move(fresh);
+    if (keyed) {
+      pb.key = c->key_buf;
+      pb.gen = c->table_gen;
+      buffer_snapshot(c, pb.bufs);
+      pb.valid = true;
+    }
+  }
+  const BatchPlan& bp = pb.bp;
   float ms = 0;
   st = batch_run(c, p, bp, o, &ms);
   if (st != PMC_OK) return st;

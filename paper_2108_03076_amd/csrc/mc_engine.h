@@ -291,17 +291,32 @@ struct alignas(sizeof(T) * P) LaneVec {
     for (int i = 0; i < P; ++i) v[i] = x;
   }
 };
-// P decisions of one lane as bits 0..P-1 of a vector register: their logic
-// is one vector instruction for all P paths (as P separate booleans it
-// became P 64-bit lane masks on the scalar unit, which bounds the stored-path
-// evaluator).
+// P decisions of one lane.  For P > 2, bits 0..P-1 of a vector register:
+// their logic is one vector instruction for all P paths (as P separate
+// booleans it became P 64-bit lane masks on the scalar unit, which bounds the
+// stored-path evaluator).  For P <= 2, P booleans (wave-wide lane masks):
+// each comparison and selection is then one vector instruction per path and
+// the logic scalar, where packing and testing bits would cost several vector
+// instructions per decision.
 template <int P>
 struct LaneMask {
+  static constexpr bool kBools = P <= 2;
   static constexpr uint32_t kAll = (1u << P) - 1u;
-  uint32_t m;
+  uint32_t m;      // P > 2
+  bool b[P];       // P <= 2
   LaneMask() = default;
-  __device__ __forceinline__ LaneMask(bool x) : m(x ? kAll : 0u) {}
-  __device__ __forceinline__ bool bit(int i) const { return (m >> i) & 1u; }
+  __device__ __forceinline__ LaneMask(bool x) {
+    if constexpr (kBools) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) b[i] = x;
+    } else {
+      m = x ? kAll : 0u;
+    }
+  }
+  __device__ __forceinline__ bool bit(int i) const {
+    if constexpr (kBools) return b[i];
+    else return (m >> i) & 1u;
+  }
 };
 template <bool B, class X, class Y> struct pick_t { using type = X; };
 template <class X, class Y> struct pick_t<false, X, Y> { using type = Y; };
@@ -339,8 +354,12 @@ PMC_VEC_BINARY(vmax, fmax(a, b))
   template <typename T, int P>                                                                      \
   __device__ __forceinline__ LaneMask<P> NAME(const LaneVec<T, P>& x, const LaneVec<T, P>& y) {     \
     LaneMask<P> r;                                                                                  \
-    r.m = 0u;                                                                                       \
-    _Pragma("unroll") for (int i = 0; i < P; ++i) r.m |= (x.v[i] OP y.v[i]) ? (1u << i) : 0u;       \
+    if constexpr (LaneMask<P>::kBools) {                                                            \
+      _Pragma("unroll") for (int i = 0; i < P; ++i) r.b[i] = x.v[i] OP y.v[i];                      \
+    } else {                                                                                        \
+      r.m = 0u;                                                                                     \
+      _Pragma("unroll") for (int i = 0; i < P; ++i) r.m |= (x.v[i] OP y.v[i]) ? (1u << i) : 0u;     \
+    }                                                                                               \
     return r;                                                                                       \
   }
 PMC_VEC_COMPARE(vlt, <)
@@ -363,22 +382,53 @@ __device__ __forceinline__ bool vall(bool a) { return __all(a); }
 template <typename T> __device__ __forceinline__ T vsel(bool c, T a, T b) { return c ? a : b; }
 template <int P> __device__ __forceinline__ LaneMask<P> vnot(const LaneMask<P>& a) {
   LaneMask<P> r;
-  r.m = a.m ^ LaneMask<P>::kAll;
+  if constexpr (LaneMask<P>::kBools) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) r.b[i] = !a.b[i];
+  } else {
+    r.m = a.m ^ LaneMask<P>::kAll;
+  }
   return r;
 }
 template <int P> __device__ __forceinline__ LaneMask<P> vand(const LaneMask<P>& a, const LaneMask<P>& b) {
   LaneMask<P> r;
-  r.m = a.m & b.m;
+  if constexpr (LaneMask<P>::kBools) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) r.b[i] = a.b[i] && b.b[i];
+  } else {
+    r.m = a.m & b.m;
+  }
   return r;
 }
 template <int P> __device__ __forceinline__ LaneMask<P> vor(const LaneMask<P>& a, const LaneMask<P>& b) {
   LaneMask<P> r;
-  r.m = a.m | b.m;
+  if constexpr (LaneMask<P>::kBools) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) r.b[i] = a.b[i] || b.b[i];
+  } else {
+    r.m = a.m | b.m;
+  }
   return r;
 }
-template <int P> __device__ __forceinline__ bool vany(const LaneMask<P>& a) { return __any(a.m != 0u); }
+template <int P> __device__ __forceinline__ bool vany(const LaneMask<P>& a) {
+  if constexpr (LaneMask<P>::kBools) {
+    bool x = false;
+#pragma unroll
+    for (int i = 0; i < P; ++i) x = x || a.b[i];
+    return __any(x);
+  } else {
+    return __any(a.m != 0u);
+  }
+}
 template <int P> __device__ __forceinline__ bool vall(const LaneMask<P>& a) {
-  return __all(a.m == LaneMask<P>::kAll);
+  if constexpr (LaneMask<P>::kBools) {
+    bool x = true;
+#pragma unroll
+    for (int i = 0; i < P; ++i) x = x && a.b[i];
+    return __all(x);
+  } else {
+    return __all(a.m == LaneMask<P>::kAll);
+  }
 }
 template <typename T, int P>
 __device__ __forceinline__ LaneVec<T, P> vsel(const LaneMask<P>& c, const LaneVec<T, P>& a, const LaneVec<T, P>& b) {
@@ -390,7 +440,12 @@ __device__ __forceinline__ LaneVec<T, P> vsel(const LaneMask<P>& c, const LaneVe
 template <int P>
 __device__ __forceinline__ LaneMask<P> vsel(const LaneMask<P>& c, const LaneMask<P>& a, const LaneMask<P>& b) {
   LaneMask<P> r;
-  r.m = (c.m & a.m) | (~c.m & b.m & LaneMask<P>::kAll);
+  if constexpr (LaneMask<P>::kBools) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) r.b[i] = c.b[i] ? a.b[i] : b.b[i];
+  } else {
+    r.m = (c.m & a.m) | (~c.m & b.m & LaneMask<P>::kAll);
+  }
   return r;
 }
 
@@ -709,12 +764,7 @@ struct GenStream {
       for (int a = 0; a < A; ++a) cur[e][a] = M.s0[a] * Num<T>::exps(x[e][a]);
     }
   }
-  __device__ __forceinline__ void prime(Win&) {}
-  __device__ __forceinline__ V read(Win&, int slot, int a) {
-    if (slot != last) {
-      if (slot < last) restart();   // never for a checked expression; kept correct
-      do { step(); } while (last < slot);
-    }
+  __device__ __forceinline__ V price_of(int a) const {
     if constexpr (P == 1) {
       return cur[0][a];
     } else {
@@ -723,6 +773,21 @@ struct GenStream {
       for (int e = 0; e < P; ++e) r.v[e] = cur[e][a];
       return r;
     }
+  }
+  __device__ __forceinline__ void prime(Win&) {}
+  // The newest slot, or the next one (one step, straight-line code: the
+  // usual reads); any other slot by the loop below -- an earlier one, which
+  // a checked expression never reads, from the spot again.
+  __device__ __forceinline__ V read(Win&, int slot, int a) {
+    if (slot != last) {
+      if (slot == last + 1) {
+        step();
+      } else {
+        if (slot < last) restart();
+        while (last < slot) step();
+      }
+    }
+    return price_of(a);
   }
   __device__ __forceinline__ V hist(int a, int day) const { return V(hist_value(histp, hist_first, n_hist, a, day)); }
 };
