@@ -113,6 +113,37 @@ int pmc_payoff_load(pmc_ctx* ctx, const char* il_text, size_t len,
                     const char* const* tvar_names, int n_tvars, pmc_payoff** out);
 void pmc_payoff_free(pmc_payoff* p);
 
+/* Contract language (CL) front end (Sec. 2, Fig. 1, with template
+ * expressions; Sec. 4, the compilation tau_c / tau_e).  Contract text:
+ *   c ::= zero | transfer(P1, P2 [, ASSET]) | scale(e, c) | translate(t, c)
+ *       | ifWithin(e, t, c, c) | if(e, c, c) | both(c, c) | all[c, ..., c]
+ *   t ::= N | NAME                      (a numeral or a template variable)
+ *   e ::= obs(LABEL, I) | F | true | false | (e) | -e | !e
+ *       | e OP e   with OP, loosest first: || ; && ; < <= > >= == ; + - ; * /
+ *       | add|sub|mult|div|min|max|lt|leq|eq|and|or(e, e) | neg|not(e)
+ *       | cond(e, e, e)
+ * if(e, c1, c2) is ifWithin(e, 0, c1, c2) (checked at the current time
+ * only); all[c1, ..., cn] abbreviates both(c1, both(..., cn)); ';' starts a
+ * comment to the end of the line.  The asset of a transfer is dropped
+ * (one currency, two-party view).  Compilation accumulates translate's
+ * shifts into the start time t0 with the smart addition of Sec. 4
+ * (numerals are added; the numeral 0 is the identity): obs(l, i) becomes
+ * (model l t0+i), transfer (payoff t0 P1 P2), scale mult, both add, zero
+ * (real 0.0), cond and if (if ...), ifWithin (loopif e c1 c2 t), and the
+ * comparisons > and >= become lt and leq with their operands swapped.
+ * pmc_contract_compile writes the payoff-language text (at most cap bytes,
+ * NUL-terminated; *il_len gets the full length; il_out may be NULL to
+ * query).  pmc_contract_load compiles and loads it as pmc_payoff_load
+ * does, with the same label arguments (observables in obs(l, i) are asset
+ * or parameter labels; template variables in t are tvar_names).
+ * Errors: PMC_E_PARSE (contract syntax, with the offset in
+ * pmc_last_error), and those of pmc_payoff_load. */
+int pmc_contract_compile(const char* cl_text, size_t len, char* il_out, size_t cap, size_t* il_len);
+int pmc_contract_load(pmc_ctx* ctx, const char* cl_text, size_t len,
+                      const char* const* asset_labels, int n_assets,
+                      const char* const* param_labels, int n_params,
+                      const char* const* tvar_names, int n_tvars, pmc_payoff** out);
+
 /* Time-parameterised payoff (Sec. 4.1, cutPayoff): a new payoff in which
  * every payoff(t, p, q) is guarded as if(t + t0 < now, 0, payoff(t, p, q)),
  * so pricing it with opts.t_now = n counts only the cashflows on days >= n

@@ -103,6 +103,9 @@ _sig = {
     "pmc_payoff_load": (_i, [_vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_char_p), _i, C.POINTER(C.c_char_p), _i,
                              C.POINTER(C.c_char_p), _i, C.POINTER(_vp)]),
     "pmc_payoff_free": (None, [_vp]),
+    "pmc_contract_compile": (_i, [C.c_char_p, C.c_size_t, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "pmc_contract_load": (_i, [_vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_char_p), _i, C.POINTER(C.c_char_p), _i,
+                               C.POINTER(C.c_char_p), _i, C.POINTER(_vp)]),
     "pmc_payoff_source": (_i, [_vp, C.POINTER(C.c_int32), C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "pmc_payoff_cut": (_i, [_vp, _vp, C.POINTER(_vp)]),
     "pmc_payoff_get_info": (_i, [_vp, C.POINTER(PayoffInfo)]),
@@ -288,6 +291,33 @@ class Payoff:
         self.ctx.check(lib.pmc_payoff_grid(self.h, tp, days.ctypes.data_as(C.POINTER(C.c_int32)),
                                            days.size, C.byref(n), C.byref(hz)))
         return days[:n.value].tolist(), hz.value
+
+
+def compile_contract(cl_text):
+    """Payoff-language text of a contract-language contract
+    (pmc_contract_compile)."""
+    b = cl_text.encode()
+    n = C.c_size_t()
+    _NoContext.check(lib.pmc_contract_compile(b, len(b), None, 0, C.byref(n)))
+    buf = C.create_string_buffer(n.value + 1)
+    _NoContext.check(lib.pmc_contract_compile(b, len(b), buf, n.value + 1, C.byref(n)))
+    return buf.value.decode()
+
+
+def load_contract(cl_text, assets, params=(), tvars=(), ctx=None):
+    """A payoff loaded from contract-language text (pmc_contract_load)."""
+    c = ctx if ctx is not None else _NoContext()
+    new = Payoff.__new__(Payoff)
+    new.h = None
+    new.ctx = c
+    new.assets, new.params, new.tvars = list(assets), list(params), list(tvars)
+    h = C.c_void_p()
+    b = cl_text.encode()
+    a, p, t = _strs(new.assets), _strs(new.params), _strs(new.tvars)
+    c.check(lib.pmc_contract_load(c.h, b, len(b), a, len(new.assets), p, len(new.params), t, len(new.tvars),
+                                  C.byref(h)))
+    new.h = h
+    return new
 
 
 def load_payoff(il, assets, params=(), tvars=(), ctx=None):

@@ -13,7 +13,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpmc.so")
 
 SOURCES = ["ilc.cpp", "api.cpp", "codegen.cpp", "risk.cpp", "mc_kernels.hip", "mlp_kernels.hip", "mlp_api.cpp",
-           "probe.hip"]
+           "probe.hip", "cl.cpp"]
 # Device engine sources embedded as text for run-time compilation of payoffs.
 ENGINE_TEXT = ["pmc_device.h", "mc_engine.h"]
 # Packed-FP32 instructions are disabled for every HIP translation unit.

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from cases import PROGRAMS
-from gpu_common import check_band, gpu_payoff, model_kw, opts_kw, oracle_problem, tie_band
+from gpu_common import check_band, ctx, gpu_payoff, model_kw, opts_kw, oracle_problem, tie_band
 
 pytestmark = pytest.mark.gpu
 
@@ -52,3 +52,23 @@ def test_program_engines_modes_and_oracle(name):
         bad = (np.abs(base - ref) > 2e-5 * scale) & ~band
         assert not bad.any(), (np.nonzero(bad)[0][:10], base[bad][:5], ref[bad][:5])
     assert np.any(base != 0.0)
+
+
+def test_contracts_loaded_from_the_contract_language_price_as_their_expressions():
+    """A workload contract loaded from contract-language text (compiled by
+    the library's front end) prices exactly as the workload's hand-written
+    payoff expression on the same stream, in both engines."""
+    import dataclasses
+    import paper_2108_03076_amd as P
+    from test_host_cl import CONTRACTS
+    for name in sorted(CONTRACTS):
+        text, cfg = CONTRACTS[name]
+        if cfg.tvars == ["T"] and cfg.tenv[0] > 300:
+            cfg = dataclasses.replace(cfg, tenv=[60])
+        a = P.load_contract(text, cfg.asset_labels, cfg.param_labels, cfg.tvars, ctx=ctx())
+        b = gpu_payoff(cfg)
+        for engine in ("interpreter", "compiled"):
+            print(f"[contract] {name} {engine}", flush=True)
+            ra = P.price(a, cfg.tenv, cfg.params, **model_kw(cfg), **opts_kw(cfg, 3000, engine=engine))
+            rb = P.price(b, cfg.tenv, cfg.params, **model_kw(cfg), **opts_kw(cfg, 3000, engine=engine))
+            assert (ra["sum"], ra["sum_sq"]) == (rb["sum"], rb["sum_sq"]), (name, engine, ra, rb)
