@@ -55,11 +55,14 @@ OPS_PHILOX = 15          # 10 rounds x (2 mul-hi, 2 mul-lo, 2 xor3) / 4 words
 OPS_IL_DOWN_AND_OUT = 4
 
 # HBM traffic of the headline kernel per launch, from two rocprofv3 --pmc
-# passes (FETCH_SIZE, WRITE_SIZE: KiB per dispatch) scaled by what the same
-# counters read for a 256 MiB device-to-device copy in the same run (FETCH
-# reads 0.5 KiB per KiB copied, WRITE 1.0).  Valid only for the engine sources
-# it was measured on (hash below); otherwise reported as null.
-TRAFFIC = {"engine_sha256": None, "fetch_kib": None, "write_kib": None, "fetch_scale": 2.0, "write_scale": 1.0}
+# passes (FETCH_SIZE, WRITE_SIZE: KiB per dispatch of the batched
+# down-and-out kernel) scaled by what the same counters read for the 1 GiB
+# device-to-device copies of the same run (FETCH reads 0.5 KiB per KiB
+# copied, WRITE 1.0; profiles/pmc_jit_mc_batched_down_and_out_counters.md).
+# Valid only for the engine sources it was measured on (hash below);
+# otherwise reported as null.
+TRAFFIC = {"engine_sha256": "f062fcd1f06cbb266bc18c63f21bfd62bba984b2fe642c21e2da62fe2b2598ba",
+           "fetch_kib": 14729.0, "write_kib": 6214.1, "fetch_scale": 2.0, "write_scale": 1.0}
 ENGINE_SOURCES = ("paper_2108_03076_amd/csrc/mc_engine.h", "paper_2108_03076_amd/csrc/pmc_device.h",
                   "paper_2108_03076_amd/csrc/codegen.cpp")
 C4_CPU_SAMPLE = (4, 1 << 12)   # oracle baseline: instances, paths each
@@ -430,7 +433,8 @@ def main():
     probes = {name: ctx.probe_valu(k) / 1e12 for k, name in
               enumerate(("fp32_fma", "int32_xor_add", "mad_u64_u32_add", "fp32_exp2_mul", "fp32_fma_with_xor"))}
     line["valu_measured_T_lane_ops_per_s"] = probes
-    line["roofline"]["frac_of_measured_fp32_fma"] = achieved / probes["fp32_fma"]
+    line["roofline"]["measured_peak"] = max(probes.values())
+    line["roofline"]["frac_of_measured_peak"] = achieved / max(probes.values())
     if want("C4sep"):
         # the same 1024 instruments as separate pmc_price calls
         print("[bench] C4 as 1024 separate calls", file=sys.stderr, flush=True)
