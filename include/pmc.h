@@ -391,8 +391,10 @@ void pmc_mlp_free(pmc_mlp* m);
 /* Number of parameters (weights and biases of all layers). */
 /* Save the network (shape, input box, y_scale and FP32 master weights) to a
  * binary file; pmc_mlp_load re-creates it on ctx's device with fresh Adam
- * state.  Errors: PMC_E_ARG (file cannot be opened or written), PMC_E_PARSE
- * (not a file written by pmc_mlp_save of a supported shape). */
+ * state.  The network's activation is the tanh form of GELU (file format
+ * 2; files of format 1, whose networks used the erf form, are refused).
+ * Errors: PMC_E_ARG (file cannot be opened or written), PMC_E_PARSE (not a
+ * file written by pmc_mlp_save of this format and a supported shape). */
 int pmc_mlp_save(const pmc_mlp* m, const char* path);
 int pmc_mlp_load(pmc_ctx* ctx, const char* path, pmc_mlp** out);
 int64_t pmc_mlp_num_params(const pmc_mlp* m);
@@ -405,14 +407,26 @@ typedef struct pmc_train_opts {
   double lr_max, lr_min; /* cosine schedule from lr_max to lr_min over total_steps */
   int64_t total_steps;
   double beta1, beta2, eps;
+  int eager;          /* 0: each step is one replay of a captured graph; 1: the
+                         same kernels launched one by one (same results) */
 } pmc_train_opts;
 /* One pass over n samples (x_dev [n][n_in] float, raw inputs; y_dev [n]
  * float prices) in order, one Adam step per full batch (a trailing partial
  * batch is skipped); *mean_loss receives the mean squared error of the
- * scaled target over the pass.  o->batch must be a multiple of 64. */
+ * scaled target over the pass.  o->batch must be a multiple of 64.  A step
+ * (forward, loss and gradients, Adam with the BF16 repack of the weights)
+ * is captured once as a HIP graph per batch size and replayed for every
+ * step; the batch position, learning rate and bias corrections are read
+ * from a device-side step record written at the start of the pass, so
+ * x_dev and y_dev may change between passes without a new capture.  The
+ * call returns after the pass has finished on the device. */
 int pmc_mlp_train_epoch(pmc_mlp* m, const float* x_dev, const float* y_dev, int64_t n,
                         const pmc_train_opts* o, double* mean_loss);
-/* Forward pass: y_dev[n] prices (float) for raw inputs x_dev[n][n_in]. */
+/* Forward pass: y_dev[n] prices (float) for raw inputs x_dev[n][n_in].
+ * The work is enqueued on the context's stream and the call returns once
+ * it is launched, like a kernel launch: y_dev is ready when that stream
+ * reaches this point (order later work on the same stream, or synchronize
+ * it, before reading y_dev; x_dev must stay valid until then). */
 int pmc_mlp_infer(pmc_mlp* m, const float* x_dev, float* y_dev, int64_t n);
 /* Prices from the surrogate with Monte Carlo as the fallback: point i, with
  * raw inputs x[i][n_in] (host memory), is priced by the network when every

@@ -10,8 +10,10 @@ numpy reference the GPU kernels are checked against:
 * parameters are flat in the order W1 b1 W2 b2 W3 b3 W4 b4, each W row-major
   [out][in] (the library's layout);
 * inputs are min-max scaled to [-1, 1]: 2 (x - lo) / (hi - lo) - 1;
-* GELU is the exact form 0.5 z (1 + erf(z / sqrt 2)); its derivative is
-  Phi(z) + z phi(z);
+* GELU is the tanh form of Hendrycks and Gimpel,
+  0.5 z (1 + tanh(u)), u = sqrt(2/pi) (z + 0.044715 z^3), with derivative
+  0.5 (1 + tanh u) + 0.5 z (1 - tanh^2 u) u'(z) (within 4.8e-4 of the erf
+  form z Phi(z) everywhere);
 * loss = mean((yhat - y / y_scale)^2); gradients by reverse-mode chain rule;
 * Adam (Kingma & Ba) with bias correction.
 """
@@ -20,7 +22,6 @@ from __future__ import annotations
 import math
 
 import numpy as np
-from scipy.special import erf
 
 
 def layer_shapes(n_in=8, width=256):
@@ -44,12 +45,17 @@ def unflatten(p, n_in=8, width=256):
     return out
 
 
+_C = math.sqrt(2.0 / math.pi)
+
+
 def gelu(z):
-    return 0.5 * z * (1.0 + erf(z / math.sqrt(2.0)))
+    return 0.5 * z * (1.0 + np.tanh(_C * (z + 0.044715 * z ** 3)))
 
 
 def gelu_grad(z):
-    return 0.5 * (1.0 + erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+    t = np.tanh(_C * (z + 0.044715 * z ** 3))
+    du = _C * (1.0 + 3.0 * 0.044715 * z * z)
+    return 0.5 * (1.0 + t) + 0.5 * z * (1.0 - t * t) * du
 
 
 def scale_inputs(x, lo, hi):

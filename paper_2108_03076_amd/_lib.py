@@ -91,7 +91,7 @@ class Greeks(C.Structure):
 class TrainOpts(C.Structure):
     _fields_ = [("batch", C.c_int), ("lr_max", C.c_double), ("lr_min", C.c_double),
                 ("total_steps", C.c_int64), ("beta1", C.c_double), ("beta2", C.c_double),
-                ("eps", C.c_double)]
+                ("eps", C.c_double), ("eager", C.c_int)]
 
 
 _vp, _i, _u64, _i64 = C.c_void_p, C.c_int, C.c_uint64, C.c_int64
@@ -444,9 +444,9 @@ class Surrogate:
         self.ctx.check(lib.pmc_mlp_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float))))
 
     def train_epoch(self, x, y, batch=4096, lr_max=1e-3, lr_min=1e-5, total_steps=1, beta1=0.9, beta2=0.999,
-                    eps=1e-8):
+                    eps=1e-8, eager=False):
         o = TrainOpts(int(batch), float(lr_max), float(lr_min), int(total_steps), float(beta1), float(beta2),
-                      float(eps))
+                      float(eps), int(bool(eager)))
         loss = C.c_double()
         self.ctx.check(lib.pmc_mlp_train_epoch(self.h, _ptr(x), _ptr(y), int(y.numel()), C.byref(o),
                                                C.byref(loss)))

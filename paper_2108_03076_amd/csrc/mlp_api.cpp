@@ -48,11 +48,30 @@ struct pmc_mlp {
   int64_t oW[4], ob[4];
   int out_[4], in_[4], outp[4], inp[4];
   Buf master, m, v, grad, lohi;
-  Buf W[4], Wt[4];
+  Buf W[4], Wt[4], Wf[4];
   // batch-sized work buffers
   int B = 0;
   Buf X, Xt, Z[3], H[3], Ht[3], Y, dZ4, dZ4t, dZ[3], dZt[3], part_loss, loss_acc, partial;
   Buf px, py;   // surrogate pricing: the in-box points and their predictions
+  int64_t gen = 0;   // bumped whenever a work buffer moves (a captured step is then stale)
+  // one training step captured as a graph (batch size B_graph, buffers of generation gen_graph)
+  Buf tstep, hyper;
+  std::vector<float> hyper_host;
+  TrainStep tstep_host{};
+  hipGraphExec_t step_exec = nullptr;
+  hipStream_t capture = nullptr;   // set while a step is being captured
+  int B_graph = 0;
+  int64_t gen_graph = -1;
+  double adam_graph[3] = {-1, -1, -1};   // beta1, beta2, eps the captured step was made with
+  ~pmc_mlp() { if (step_exec) (void)hipGraphExecDestroy(step_exec); }
+  MlpLayers layers() {
+    MlpLayers L;
+    for (int l = 0; l < 4; ++l) {
+      L.oW[l] = oW[l]; L.ob[l] = ob[l]; L.out[l] = out_[l]; L.in[l] = in_[l]; L.outp[l] = outp[l];
+      L.inp[l] = inp[l]; L.W[l] = W[l].as<__bf16>(); L.Wt[l] = Wt[l].as<__bf16>(); L.Wf[l] = Wf[l].as<__bf16>();
+    }
+    return L;
+  }
 };
 
 #define MLP_TRY(m, expr)                                                                           \
@@ -65,11 +84,15 @@ struct pmc_mlp {
 
 namespace {
 
+// The stream the surrogate's work goes to: the context's, or while a
+// training step is captured the capturing stream.
+hipStream_t stream_of(const pmc_mlp* M) { return M->capture ? M->capture : ctx_stream(M->ctx); }
+
 int pack_all(pmc_mlp* M) {
-  hipStream_t s = ctx_stream(M->ctx);
+  hipStream_t s = stream_of(M);
   for (int l = 0; l < 4; ++l)
     MLP_TRY(M, mlp_pack(M->master.as<float>() + M->oW[l], M->out_[l], M->in_[l], M->outp[l], M->inp[l],
-                        M->W[l].as<__bf16>(), M->Wt[l].as<__bf16>(), s));
+                        M->W[l].as<__bf16>(), M->Wt[l].as<__bf16>(), M->Wf[l].as<__bf16>(), s));
   return PMC_OK;
 }
 
@@ -93,17 +116,18 @@ int ensure_batch(pmc_mlp* M, int B) {
   MLP_TRY(M, M->loss_acc.ensure(8));
   MLP_TRY(M, M->partial.ensure((size_t)kSplits * W * W * 4));
   M->B = B;
+  M->gen++;
   return PMC_OK;
 }
 
-// Forward pass over B rows (n real) of raw inputs x; saves what backward needs
-// when train is set.
-int forward(pmc_mlp* M, const float* x, int n, int B, bool train) {
-  hipStream_t s = ctx_stream(M->ctx);
+// Forward pass over B rows (n real) of raw inputs x (with ts: the step
+// record's batch); saves what backward needs when train is set.
+int forward(pmc_mlp* M, const float* x, int n, int B, bool train, const TrainStep* ts = nullptr) {
+  hipStream_t s = stream_of(M);
   const int W = M->width;
   const float* w = M->master.as<float>();
   MLP_TRY(M, mlp_scale_inputs(x, n, M->n_in, M->lohi.as<float>(), M->lohi.as<float>() + 32, B,
-                              M->X.as<__bf16>(), M->Xt.as<__bf16>(), s));
+                              M->X.as<__bf16>(), M->Xt.as<__bf16>(), ts, s));
   const __bf16* in = M->X.as<__bf16>();
   int ld = 16;
   for (int l = 0; l < 3; ++l) {
@@ -122,14 +146,15 @@ int forward(pmc_mlp* M, const float* x, int n, int B, bool train) {
 }
 
 // Loss and gradients (into M->grad) of mean((yhat - y/y_scale)^2) over n
-// rows; adds the batch's sum of squared errors to loss_acc.
-int backward(pmc_mlp* M, const float* y, int n, int B) {
-  hipStream_t s = ctx_stream(M->ctx);
+// rows (targets y, or with ts the step record's batch); adds the batch's sum
+// of squared errors to loss_acc.
+int backward(pmc_mlp* M, const float* y, int n, int B, const TrainStep* ts = nullptr) {
+  hipStream_t s = stream_of(M);
   const int W = M->width;
   float* g = M->grad.as<float>();
   MLP_TRY(M, mlp_loss(M->Y.as<float>(), y, n, B, (float)(1.0 / M->y_scale), 2.0f / (float)n,
                       M->dZ4.as<__bf16>(), M->dZ4t.as<__bf16>(), M->part_loss.as<double>(),
-                      M->loss_acc.as<double>(), s));
+                      M->loss_acc.as<double>(), ts, s));
   float* part = M->partial.as<float>();
   // layer 4: dW4 = dZ4^T H3, db4, dZ3 = (dZ4 W4) * gelu'(Z3)
   MLP_TRY(M, mlp_gemm_f32(32, W, B, M->dZ4t.as<__bf16>(), B, M->Ht[2].as<__bf16>(), B, kSplits, part, W, s));
@@ -216,6 +241,7 @@ extern "C" int pmc_mlp_create(pmc_ctx* ctx, int n_in, int width, uint64_t seed, 
   for (int l = 0; l < 4; ++l) {
     MLP_TRY(m, m->W[l].ensure((size_t)m->outp[l] * m->inp[l] * 2));
     MLP_TRY(m, m->Wt[l].ensure((size_t)m->outp[l] * m->inp[l] * 2));
+    MLP_TRY(m, m->Wf[l].ensure((size_t)m->outp[l] * m->inp[l] * 2));
   }
   MLP_TRY(m, hipMemcpyAsync(m->master.p, h.data(), pb, hipMemcpyHostToDevice, s));
   MLP_TRY(m, hipMemsetAsync(m->m.p, 0, pb, s));
@@ -262,16 +288,17 @@ extern "C" int pmc_mlp_set_params(pmc_mlp* m, const float* in) {
 extern "C" int pmc_mlp_infer(pmc_mlp* m, const float* x, float* y, int64_t n) {
   if (!m || !x || !y || n < 1 || n > (1ll << 30)) return PMC_E_ARG;
   hipStream_t s = ctx_stream(m->ctx);
-  if (m->width == 256) {   // one fused kernel: all four layers per block of 128 samples
+  // enqueued on the context's stream only: the caller orders its use of y
+  // on that stream (or synchronizes)
+  if (m->width == 256) {   // one fused kernel: all four layers per block of 64 samples
     const float* w = m->master.as<float>();
     const int chunk = 1 << 24;
     for (int64_t o = 0; o < n; o += chunk) {
       const int k = (int)std::min<int64_t>(chunk, n - o);
-      MLP_TRY(m, mlp_infer256(x + o * m->n_in, k, m->n_in, m->lohi.as<float>(), m->W[0].as<__bf16>(), w + m->ob[0],
-                              m->W[1].as<__bf16>(), w + m->ob[1], m->W[2].as<__bf16>(), w + m->ob[2],
-                              m->W[3].as<__bf16>(), w + m->ob[3], (float)m->y_scale, y + o, s));
+      MLP_TRY(m, mlp_infer256(x + o * m->n_in, k, m->n_in, m->lohi.as<float>(), m->Wf[0].as<__bf16>(), w + m->ob[0],
+                              m->Wf[1].as<__bf16>(), w + m->ob[1], m->Wf[2].as<__bf16>(), w + m->ob[2],
+                              m->Wf[3].as<__bf16>(), w + m->ob[3], (float)m->y_scale, y + o, s));
     }
-    MLP_TRY(m, hipStreamSynchronize(s));
     return PMC_OK;
   }
   const int chunk = 1 << 16;
@@ -285,7 +312,6 @@ extern "C" int pmc_mlp_infer(pmc_mlp* m, const float* x, float* y, int64_t n) {
     // the k real rows of the prices (network output times y_scale)
     MLP_TRY(m, hipMemcpyAsync(y + o, m->Y.p, (size_t)k * sizeof(float), hipMemcpyDeviceToDevice, s));
   }
-  MLP_TRY(m, hipStreamSynchronize(s));
   return PMC_OK;
 }
 
@@ -308,35 +334,111 @@ extern "C" int pmc_mlp_loss_grad(pmc_mlp* m, const float* x, const float* y, int
   return PMC_OK;
 }
 
+namespace {
+
+// Learning rate (cosine schedule) and Adam bias corrections of Adam step
+// number `step` (1-based), as the FP32 values the update uses; the moving
+// averages use the FP32 betas, and so do their bias corrections.
+void step_hyper(const pmc_train_opts* o, int64_t step, float out[3]) {
+  const double frac = std::min(1.0, (double)(step - 1) / (double)o->total_steps);
+  const double lr = o->lr_min + 0.5 * (o->lr_max - o->lr_min) * (1.0 + std::cos(M_PI * frac));
+  const float b1 = (float)o->beta1, b2 = (float)o->beta2;
+  out[0] = (float)lr;
+  out[1] = (float)(1.0 - std::pow((double)b1, (double)step));
+  out[2] = (float)(1.0 - std::pow((double)b2, (double)step));
+}
+
+// One training step over batch ts->step of the step record: forward, loss
+// and gradients, Adam with the BF16 repack, then the record's next step.
+int enqueue_step(pmc_mlp* M, const pmc_train_opts* o, int B, TrainStep* ts) {
+  int rc = forward(M, nullptr, B, B, true, ts);
+  if (rc == PMC_OK) rc = backward(M, nullptr, B, B, ts);
+  if (rc != PMC_OK) return rc;
+  hipStream_t s = stream_of(M);
+  MLP_TRY(M, mlp_adam_pack(M->master.as<float>(), M->m.as<float>(), M->v.as<float>(), M->grad.as<float>(),
+                           M->n_params, 0.0f, (float)o->beta1, (float)o->beta2, (float)o->eps, 1.0f, 1.0f,
+                           M->layers(), ts, s));
+  MLP_TRY(M, mlp_step_next(ts, s));
+  return PMC_OK;
+}
+
+// The training step captured as a graph for batch size B, the current work
+// buffers and the Adam constants (betas, eps); captured again when any of
+// them changes.  The batch position, the learning rate and the bias
+// corrections come from the step record, so one graph serves every step of
+// every epoch.  No memset is captured.
+int step_graph(pmc_mlp* M, const pmc_train_opts* o, int B) {
+  if (M->step_exec && M->B_graph == B && M->gen_graph == M->gen && M->adam_graph[0] == o->beta1 &&
+      M->adam_graph[1] == o->beta2 && M->adam_graph[2] == o->eps)
+    return PMC_OK;
+  if (M->step_exec) { (void)hipGraphExecDestroy(M->step_exec); M->step_exec = nullptr; }
+  hipStream_t cap = nullptr;
+  MLP_TRY(M, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    return ctx_fail(M->ctx, PMC_E_HIP, std::string("training step capture: ") + hipGetErrorString(e));
+  }
+  M->capture = cap;
+  const int rc = enqueue_step(M, o, B, M->tstep.as<TrainStep>());
+  M->capture = nullptr;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cap, &graph);
+  (void)hipStreamDestroy(cap);
+  if (rc != PMC_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+  if (e != hipSuccess)
+    return ctx_fail(M->ctx, PMC_E_HIP, std::string("training step capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&M->step_exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    M->step_exec = nullptr;
+    return ctx_fail(M->ctx, PMC_E_HIP, std::string("training step graph: ") + hipGetErrorString(e));
+  }
+  M->B_graph = B;
+  M->gen_graph = M->gen;
+  M->adam_graph[0] = o->beta1; M->adam_graph[1] = o->beta2; M->adam_graph[2] = o->eps;
+  return PMC_OK;
+}
+
+}  // namespace
+
 extern "C" int pmc_mlp_train_epoch(pmc_mlp* m, const float* x, const float* y, int64_t n, const pmc_train_opts* o,
                                    double* mean_loss) {
   if (!m || !x || !y || !o || n < 1) return PMC_E_ARG;
   if (o->batch < 64 || o->batch % 64 || o->batch > (1 << 20) || o->total_steps < 1 || !(o->lr_max > 0) ||
-      !(o->lr_min >= 0) || !(o->beta1 >= 0 && o->beta1 < 1) || !(o->beta2 >= 0 && o->beta2 < 1) || !(o->eps > 0))
+      !(o->lr_min >= 0) || !(o->beta1 >= 0 && o->beta1 < 1) || !(o->beta2 >= 0 && o->beta2 < 1) || !(o->eps > 0) ||
+      (o->eager != 0 && o->eager != 1))
     return ctx_fail(m->ctx, PMC_E_ARG, "bad training options (batch must be a multiple of 64)");
   hipStream_t s = ctx_stream(m->ctx);
   const int B = o->batch;
-  int rc = ensure_batch(m, B);
-  if (rc != PMC_OK) return rc;
-  MLP_TRY(m, hipMemsetAsync(m->loss_acc.p, 0, 8, s));
   const int64_t steps = n / B;   // full batches only
   if (steps < 1) return ctx_fail(m->ctx, PMC_E_ARG, "fewer samples than one batch");
-  for (int64_t k = 0; k < steps; ++k) {
-    rc = forward(m, x + k * B * m->n_in, B, B, true);
-    if (rc == PMC_OK) rc = backward(m, y + k * B, B, B);
+  int rc = ensure_batch(m, B);
+  if (rc != PMC_OK) return rc;
+  // the step record of this epoch: its batches and each step's hyper-parameters
+  MLP_TRY(m, hipSetDevice(ctx_device(m->ctx)));
+  MLP_TRY(m, m->tstep.ensure(sizeof(TrainStep)));
+  MLP_TRY(m, m->hyper.ensure((size_t)steps * 3 * sizeof(float)));
+  // the previous epoch's uploads must be done before their host copies change
+  MLP_TRY(m, hipStreamSynchronize(s));
+  m->hyper_host.resize((size_t)steps * 3);
+  for (int64_t k = 0; k < steps; ++k) step_hyper(o, m->step + 1 + k, &m->hyper_host[(size_t)k * 3]);
+  m->tstep_host = TrainStep{x, y, m->hyper.as<float>(), 0};
+  MLP_TRY(m, hipMemcpyAsync(m->hyper.p, m->hyper_host.data(), m->hyper_host.size() * sizeof(float),
+                            hipMemcpyHostToDevice, s));
+  MLP_TRY(m, hipMemcpyAsync(m->tstep.p, &m->tstep_host, sizeof(TrainStep), hipMemcpyHostToDevice, s));
+  MLP_TRY(m, hipMemsetAsync(m->loss_acc.p, 0, 8, s));
+  if (o->eager) {
+    for (int64_t k = 0; k < steps; ++k) {
+      rc = enqueue_step(m, o, B, m->tstep.as<TrainStep>());
+      if (rc != PMC_OK) return rc;
+    }
+  } else {
+    rc = step_graph(m, o, B);
     if (rc != PMC_OK) return rc;
-    const double frac = std::min(1.0, (double)m->step / (double)o->total_steps);
-    const double lr = o->lr_min + 0.5 * (o->lr_max - o->lr_min) * (1.0 + std::cos(M_PI * frac));
-    m->step++;
-    // the moving averages use the FP32 betas: so do their bias corrections
-    const float b1 = (float)o->beta1, b2 = (float)o->beta2;
-    const double c1 = 1.0 - std::pow((double)b1, (double)m->step);
-    const double c2 = 1.0 - std::pow((double)b2, (double)m->step);
-    MLP_TRY(m, mlp_adam(m->master.as<float>(), m->m.as<float>(), m->v.as<float>(), m->grad.as<float>(),
-                        (int)m->n_params, (float)lr, b1, b2, (float)o->eps, (float)c1, (float)c2, s));
-    rc = pack_all(m);
-    if (rc != PMC_OK) return rc;
+    for (int64_t k = 0; k < steps; ++k) MLP_TRY(m, hipGraphLaunch(m->step_exec, s));
   }
+  m->step += steps;
   double acc = 0;
   MLP_TRY(m, hipMemcpyAsync(&acc, m->loss_acc.p, 8, hipMemcpyDeviceToHost, s));
   MLP_TRY(m, hipStreamSynchronize(s));
@@ -427,10 +529,12 @@ extern "C" int pmc_mlp_price(pmc_mlp* m, const double* x, int64_t n, const pmc_p
   return PMC_OK;
 }
 
-// File layout (native byte order): the 8 bytes "PMCMLP1\n", int32 n_in,
+// File layout (native byte order): the 8 bytes "PMCMLP2\n", int32 n_in,
 // int32 width, float64 y_scale, float64 lo[n_in], float64 hi[n_in],
 // int64 n_params, float32 master weights [n_params] (W1 b1 .. W4 b4).
-static const char kMlpMagic[8] = {'P', 'M', 'C', 'M', 'L', 'P', '1', '\n'};
+// Format 2 is the network with the tanh form of GELU; format 1 files (the
+// erf form) are refused, since their weights belong to another function.
+static const char kMlpMagic[8] = {'P', 'M', 'C', 'M', 'L', 'P', '2', '\n'};
 
 extern "C" int pmc_mlp_save(const pmc_mlp* m, const char* path) {
   if (!m || !path) return PMC_E_ARG;

@@ -5,6 +5,27 @@
 
 namespace pmc {
 
+// Where a captured training step finds what changes from step to step:
+// the epoch's inputs and targets (batch `step` of B rows each) and the
+// per-step learning rate and Adam bias corrections (hyper[3 * step + 0..2]).
+// Device memory; the last kernel of a step increments `step`.
+struct TrainStep {
+  const float* x;
+  const float* y;
+  const float* hyper;
+  int64_t step;
+};
+
+// The four layers' places in the flat parameter vector and their BF16
+// copies (for the fused Adam and repack).
+struct MlpLayers {
+  int64_t oW[4], ob[4];
+  int out[4], in[4], outp[4], inp[4];
+  __bf16* W[4];
+  __bf16* Wt[4];
+  __bf16* Wf[4];   // fragment-ordered copies (fused inference)
+};
+
 // C [M x N] FP32 (split-K: `splits` partial products, C[z][M][ldc]) = A Bt^T.
 hipError_t mlp_gemm_f32(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb, int splits,
                         float* C, int ldc, hipStream_t s);
@@ -20,21 +41,29 @@ hipError_t mlp_gemm_out(int M, int N, int K, const __bf16* A, int lda, const __b
 // Back-propagation through a hidden layer: dZ = (A Bt^T) * gelu'(Z), and dZ^T.
 hipError_t mlp_gemm_back_hidden(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb,
                                 const float* Z, __bf16* dZ, __bf16* dZt, hipStream_t s);
+// x raw inputs [n][n_in] (or, with ts, the step record's batch).
 hipError_t mlp_scale_inputs(const float* x, int n, int n_in, const float* lo, const float* hi, int B, __bf16* X,
-                            __bf16* Xt, hipStream_t s);
+                            __bf16* Xt, const TrainStep* ts, hipStream_t s);
+// t targets [n] (or, with ts, the step record's batch).
 hipError_t mlp_loss(const float* yhat, const float* t, int n, int B, float inv_scale, float grad_scale, __bf16* dZ,
-                    __bf16* dZt, double* part, double* acc, hipStream_t s);
+                    __bf16* dZt, double* part, double* acc, const TrainStep* ts, hipStream_t s);
 hipError_t mlp_reduce_splits(const float* partial, int splits, size_t zstride, int ldp, int rows, int cols,
                              float* g, hipStream_t s);
 hipError_t mlp_rowsum(const __bf16* dZt, int B, int rows, float* g, hipStream_t s);
-hipError_t mlp_adam(float* w, float* m, float* v, const float* g, int n, float lr, float b1, float b2, float eps,
-                    float c1, float c2, hipStream_t s);
+// Adam on the FP32 master parameters and the BF16 repack of the weights
+// (with ts: lr, c1, c2 from its current step).
+hipError_t mlp_adam_pack(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
+                         float eps, float c1, float c2, const MlpLayers& L, const TrainStep* ts, hipStream_t s);
+hipError_t mlp_step_next(TrainStep* ts, hipStream_t s);
+// W [out_pad][in_pad], Wt [in_pad][out_pad] and the fragment-ordered Wf
+// (A-operand fragments of 32-row output tiles and 16-wide k steps, each
+// 64 lanes x 16 bytes, tile-major) from the FP32 master weights.
 hipError_t mlp_pack(const float* master, int out, int in, int out_pad, int in_pad, __bf16* W, __bf16* Wt,
-                    hipStream_t s);
+                    __bf16* Wf, hipStream_t s);
 // Fused inference of the width-256 network for n samples: y[i] = price of
 // row i of x [n][n_in] (lohi: the input box, lo[0..31] then hi[0..31]; W1
-// [256][16], W2 and W3 [256][256], W4 [32][256] padded BF16 weights; b*
-// FP32 biases).
+// [256][16], W2 and W3 [256][256], W4 [32][256] padded BF16 weights in
+// fragment order (mlp_pack's Wf); b* FP32 biases).
 hipError_t mlp_infer256(const float* x, int n, int n_in, const float* lohi, const __bf16* W1, const float* b1,
                         const __bf16* W2, const float* b2, const __bf16* W3, const float* b3, const __bf16* W4,
                         const float* b4, float y_scale, float* y, hipStream_t s);

@@ -15,29 +15,37 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 __device__ __forceinline__ float from_bf16(__bf16 x) { return (float)x; }
 
-// erf by Abramowitz & Stegun 7.1.26 (Hastings' rational form):
-// erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-x^2},
-// t = 1 / (1 + p x), x >= 0, |error| <= 1.5e-7 (far below the BF16 rounding
-// of the activations it feeds); odd symmetry for x < 0.
-__device__ __forceinline__ float erf_as(float v) {
-  const float x = fabsf(v);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
-  float q = fmaf(1.061405429f, t, -1.453152027f);
-  q = fmaf(q, t, 1.421413741f);
-  q = fmaf(q, t, -0.284496736f);
-  q = fmaf(q, t, 0.254829592f);
-  const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * x * x);
-  return copysignf(fmaf(-q * t, e, 1.0f), v);
+// Position of weight (o, k) of a layer with in_pad inputs in the
+// fragment-ordered copy the fused inference reads: the 16-byte A-operand
+// fragment of output tile o/32 at k step k/16 that lane o%32 + 32 ((k%16)/8)
+// supplies, fragments stored one after another (tile-major, then k step),
+// so a wave's fragment load reads 1 KB of consecutive bytes.
+__device__ __forceinline__ size_t frag_index(int o, int k, int in_pad) {
+  const int ks = in_pad / 16;
+  const int f = (o >> 5) * ks + (k >> 4);
+  const int lane = (o & 31) + 32 * ((k & 15) >> 3);
+  return ((size_t)f * 64 + lane) * 8 + (k & 7);
 }
-// GELU with the erf form and its derivative (the same erf in training and
-// inference).
-__device__ __forceinline__ float gelu(float z) {
-  const float h = 0.5f * z;
-  return fmaf(h, erf_as(z * 0.70710678118654752f), h);
+
+// GELU in the tanh form of Hendrycks and Gimpel,
+// gelu(z) = z/2 (1 + tanh(u)), u = sqrt(2/pi) (z + 0.044715 z^3),
+// evaluated as z * sigma(2u) = z / (1 + 2^(z (A + B z^2))) with
+// A = -2 sqrt(2/pi) log2(e), B = 0.044715 A: two multiplies, an FMA, an
+// add, exp2 and a reciprocal.  For z -> -inf the exponential overflows to
+// +inf and the result is -0; for z -> +inf it is z.
+constexpr float kGeluA = -2.302208198144325f;
+constexpr float kGeluB = -0.1029432395800235f;
+__device__ __forceinline__ float gelu_sigma(float z) {
+  const float v = fmaf(z * z, kGeluB, kGeluA) * z;
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(v));
 }
+__device__ __forceinline__ float gelu(float z) { return z * gelu_sigma(z); }
+// d/dz of z sigma(2u): sigma + z sigma (1 - sigma) 2u'(z),
+// 2u' = 2 sqrt(2/pi) (1 + 3 * 0.044715 z^2).
 __device__ __forceinline__ float gelu_grad(float z) {
-  return fmaf(0.5f, erf_as(z * 0.70710678118654752f), 0.5f) +
-         z * 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z);
+  const float r = gelu_sigma(z);
+  const float du = fmaf(z * z, 0.21406444881780073f, 1.5957691216057308f);
+  return fmaf(z * r * (1.0f - r), du, r);
 }
 
 // C = A * Bt^T with A [M x K] and Bt [N x K] row-major BF16 (K contiguous).
@@ -46,10 +54,17 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // k_chunk multiples of 16, lda/ldb multiples of 8 (16-byte rows).
 // MFMA operand layout (32x32x16): lane l supplies row l%32 of A (and of Bt)
 // at k = 8*(l/32) .. +7; accumulator element e of lane l is
-// C[8*(e/4) + 4*(l/32) + e%4][l%32].
+// C[8*(e/4) + 4*(l/32) + e%4][l%32].  The k loop issues four steps' loads
+// before their products.  An epilogue with a transposed BF16 output
+// (Epi::kTransposed) returns each element's transposed value; the wave
+// stages its 32 x 32 tile in LDS as [column][row] and writes each column's
+// 32 rows as one 64-byte segment (the scattered 2-byte stores of a direct
+// transposed write cost more than the products).
 template <class Epi>
 __global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const __bf16* __restrict__ A, int lda,
                                                  const __bf16* __restrict__ Bt, int ldb, int k_chunk, Epi epi) {
+  constexpr int kTld = 40;   // staged tile row: 32 rows + 8 padding
+  __shared__ __bf16 tt[Epi::kTransposed ? 4 * 32 * kTld : 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
   const int n0 = blockIdx.x * 64 + (w & 1) * 32;
@@ -60,58 +75,111 @@ __global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const __bf
   const __bf16* pa = A + (size_t)(m0 + r) * lda + kh;
   const __bf16* pb = Bt + (size_t)(n0 + r) * ldb + kh;
   f32x16 acc;
+  const float a0 = epi.init(n0 + r);
 #pragma unroll
-  for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
-  for (int k = kbeg; k < kend; k += 16) {
+  for (int e = 0; e < 16; ++e) acc[e] = a0;
+  int k = kbeg;
+  for (; k + 64 <= kend; k += 64) {
+    bf16x8 a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = *reinterpret_cast<const bf16x8*>(pa + k + 16 * u);
+      b[u] = *reinterpret_cast<const bf16x8*>(pb + k + 16 * u);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u], b[u], acc, 0, 0, 0);
+  }
+  for (; k < kend; k += 16) {
     const bf16x8 a = *reinterpret_cast<const bf16x8*>(pa + k);
     const bf16x8 b = *reinterpret_cast<const bf16x8*>(pb + k);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
   }
   const int col = n0 + r;
+  if constexpr (Epi::kTransposed) {
+    __bf16* t = tt + w * 32 * kTld;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int row = m0 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-    epi(row, col, acc[e], (int)blockIdx.z);
+    for (int e = 0; e < 16; ++e) {
+      const int rl = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      t[r * kTld + rl] = epi(m0 + rl, col, acc[e], (int)blockIdx.z);
+    }
+    // the wave reads back what its lanes wrote (the fence orders the LDS
+    // stores before the loads); lane l copies rows 16 (l%2) .. +15 of tile
+    // column l/2
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int c = lane >> 1, h = (lane & 1) * 16;
+    const bf16x8 v0 = *reinterpret_cast<const bf16x8*>(t + c * kTld + h);
+    const bf16x8 v1 = *reinterpret_cast<const bf16x8*>(t + c * kTld + h + 8);
+    epi.store_t(n0 + c, m0 + h, v0, v1);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int row = m0 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      epi(row, col, acc[e], (int)blockIdx.z);
+    }
   }
 }
 
+// Each epilogue also names the accumulators' starting value for an output
+// column: the layer's bias (the matrix cores add the products to it), or 0.
 struct EpiF32 {          // C[z][row][col] (split-K partials or plain output)
+  static constexpr bool kTransposed = false;
   float* c; int ldc; size_t zstride;
+  __device__ float init(int) const { return 0.0f; }
   __device__ void operator()(int row, int col, float v, int z) const { c[z * zstride + (size_t)row * ldc + col] = v; }
 };
 
-struct EpiHidden {       // z = v + b; Z = z; H = gelu(z) (BF16) and its transpose
+struct EpiHidden {       // z = b + v; Z = z; H = gelu(z) (BF16) and its transpose
+  static constexpr bool kTransposed = true;
   const float* bias; float* Z; int ldz; __bf16* H; int ldh; __bf16* Ht; int ldht;
-  __device__ void operator()(int row, int col, float v, int) const {
-    const float z = v + bias[col];
+  __device__ float init(int col) const { return bias[col]; }
+  __device__ __bf16 operator()(int row, int col, float z, int) const {
     Z[(size_t)row * ldz + col] = z;
     const __bf16 h = to_bf16(gelu(z));
     H[(size_t)row * ldh + col] = h;
-    Ht[(size_t)col * ldht + row] = h;
+    return h;
+  }
+  // Ht[col][row .. row + 15]
+  __device__ void store_t(int col, int row, bf16x8 v0, bf16x8 v1) const {
+    bf16x8* p = reinterpret_cast<bf16x8*>(Ht + (size_t)col * ldht + row);
+    p[0] = v0;
+    p[1] = v1;
   }
 };
 
-struct EpiHiddenInfer {  // H = gelu(v + b) (BF16) only
+struct EpiHiddenInfer {  // H = gelu(b + v) (BF16) only
+  static constexpr bool kTransposed = false;
   const float* bias; __bf16* H; int ldh;
-  __device__ void operator()(int row, int col, float v, int) const {
-    H[(size_t)row * ldh + col] = to_bf16(gelu(v + bias[col]));
+  __device__ float init(int col) const { return bias[col]; }
+  __device__ void operator()(int row, int col, float z, int) const {
+    H[(size_t)row * ldh + col] = to_bf16(gelu(z));
   }
 };
 
-struct EpiOut {          // y = (v + b) * scale for output column 0
+struct EpiOut {          // y = (b + v) * scale for output column 0
+  static constexpr bool kTransposed = false;
   const float* bias; float* y; float scale;
+  __device__ float init(int col) const { return col == 0 ? bias[0] : 0.0f; }
   __device__ void operator()(int row, int col, float v, int) const {
-    if (col == 0) y[row] = (v + bias[0]) * scale;
+    if (col == 0) y[row] = v * scale;
   }
 };
 
 struct EpiBackHidden {   // dZ = dH * gelu'(Z) (BF16) and its transpose
+  static constexpr bool kTransposed = true;
   const float* Z; int ldz; __bf16* dZ; int lddz; __bf16* dZt; int lddzt;
-  __device__ void operator()(int row, int col, float v, int) const {
+  __device__ float init(int) const { return 0.0f; }
+  // dZt[col][row .. row + 15]
+  __device__ void store_t(int col, int row, bf16x8 v0, bf16x8 v1) const {
+    bf16x8* p = reinterpret_cast<bf16x8*>(dZt + (size_t)col * lddzt + row);
+    p[0] = v0;
+    p[1] = v1;
+  }
+  __device__ __bf16 operator()(int row, int col, float v, int) const {
     const float g = v * gelu_grad(Z[(size_t)row * ldz + col]);
     const __bf16 b = to_bf16(g);
     dZ[(size_t)row * lddz + col] = b;
-    dZt[(size_t)col * lddzt + row] = b;
+    return b;
   }
 };
 
@@ -128,27 +196,38 @@ hipError_t gemm(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt,
 
 // x raw [n][n_in] -> X [B][16] BF16 scaled to [-1,1] (columns >= n_in zero)
 // and its transpose Xt [32][B] (rows >= n_in zero).  Rows >= n are zero.
+// With a step record, x is its batch of the current step instead.
 __global__ void k_scale_inputs(const float* __restrict__ x, int n, int n_in, const float* __restrict__ lo,
-                               const float* __restrict__ hi, int B, __bf16* X, __bf16* Xt) {
+                               const float* __restrict__ hi, int B, __bf16* __restrict__ X,
+                               __bf16* __restrict__ Xt, const TrainStep* __restrict__ ts) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= B) return;
+  if (ts) x = ts->x + ts->step * (int64_t)B * n_in;
+  bf16x8 row[2];
+#pragma unroll
   for (int j = 0; j < 32; ++j) {
     float v = 0.0f;
     if (i < n && j < n_in) v = 2.0f * (x[(size_t)i * n_in + j] - lo[j]) / (hi[j] - lo[j]) - 1.0f;
     const __bf16 b = to_bf16(v);
-    if (j < 16) X[(size_t)i * 16 + j] = b;
+    if (j < 16) row[j >> 3][j & 7] = b;
     Xt[(size_t)j * B + i] = b;
   }
+  bf16x8* px = reinterpret_cast<bf16x8*>(X + (size_t)i * 16);
+  px[0] = row[0];
+  px[1] = row[1];
 }
 
 // dy = 2 (yhat - t) / n_total for real rows (0 for padding), stored as the
 // first column of dZ4 [B][32] and first row of dZ4t [32][B]; per-block sums
 // of (yhat - t)^2 into part[block].
+// With a step record, t is its batch of the current step instead.
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ yhat, const float* __restrict__ t, int n,
-                                              int B, float inv_scale, float grad_scale, __bf16* dZ, __bf16* dZt,
-                                              double* part) {
+                                              int B, float inv_scale, float grad_scale, __bf16* __restrict__ dZ,
+                                              __bf16* __restrict__ dZt, double* __restrict__ part,
+                                              const TrainStep* __restrict__ ts) {
   __shared__ double red[256];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ts) t = ts->y + ts->step * (int64_t)B;
   double l = 0.0;
   if (i < B) {
     float d = 0.0f;
@@ -158,10 +237,13 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ yhat, co
       d = grad_scale * e;
     }
     const __bf16 b = to_bf16(d);
-    for (int j = 0; j < 32; ++j) {
-      dZ[(size_t)i * 32 + j] = j == 0 ? b : to_bf16(0.0f);
-      dZt[(size_t)j * B + i] = j == 0 ? b : to_bf16(0.0f);
-    }
+    bf16x8 first, zero;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) { first[j] = to_bf16(0.0f); zero[j] = to_bf16(0.0f); }
+    first[0] = b;
+    bf16x8* pz = reinterpret_cast<bf16x8*>(dZ + (size_t)i * 32);
+    pz[0] = first; pz[1] = zero; pz[2] = zero; pz[3] = zero;
+    for (int j = 0; j < 32; ++j) dZt[(size_t)j * B + i] = j == 0 ? b : to_bf16(0.0f);
   }
   red[threadIdx.x] = l;
   __syncthreads();
@@ -192,40 +274,70 @@ __global__ void k_reduce_splits(const float* __restrict__ partial, int splits, s
   g[i] = s;
 }
 
-// g[r] = sum over b of dZt[r][b] (BF16), one block per row, fixed order.
+// g[r] = sum over b of dZt[r][b] (BF16) in a fixed order: one wave per row,
+// lane l sums elements 8 (l + 64 i) .. + 7 for i = 0, 1, .. (16-byte loads),
+// then the lanes' sums are added pairwise by a butterfly.  B a multiple of
+// 8.
 __global__ __launch_bounds__(256) void k_rowsum(const __bf16* __restrict__ dZt, int B, int rows_real,
                                                 float* __restrict__ g) {
-  __shared__ float red[256];
-  const int r = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= rows_real) return;
+  const __bf16* p = dZt + (size_t)r * B;
   float s = 0.0f;
-  for (int b = threadIdx.x; b < B; b += blockDim.x) s += from_bf16(dZt[(size_t)r * B + b]);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+  for (int b = 8 * lane; b < B; b += 512) {
+    const bf16x8 v = *reinterpret_cast<const bf16x8*>(p + b);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += from_bf16(v[j]);
   }
-  if (threadIdx.x == 0) g[r] = red[0];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) g[r] = s;
 }
 
-__global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
-                       const float* __restrict__ g, int n, float lr, float b1, float b2, float eps, float c1,
-                       float c2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One Adam step on the FP32 master parameters followed by the BF16 copies
+// W [out_pad][in_pad] and Wt [in_pad][out_pad] of each updated weight (the
+// zero padding is written once, at creation).  With a step record, the
+// learning rate and the bias corrections are its entries for the current
+// step.
+__global__ void k_adam_pack(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g, int64_t n, float lr, float b1, float b2, float eps,
+                            float c1, float c2, MlpLayers L, const TrainStep* __restrict__ ts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (ts) {
+    const float* h = ts->hyper + 3 * ts->step;
+    lr = h[0]; c1 = h[1]; c2 = h[2];
+  }
   const float gi = g[i];
   const float mi = b1 * m[i] + (1.0f - b1) * gi;
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+#pragma unroll
+  for (int l = 0; l < 4; ++l)
+    if (i >= L.oW[l] && i < L.ob[l]) {
+      const int64_t j = i - L.oW[l];
+      const int o = (int)(j / L.in[l]), k = (int)(j % L.in[l]);
+      const __bf16 b = to_bf16(wi);
+      L.W[l][(size_t)o * L.inp[l] + k] = b;
+      L.Wt[l][(size_t)k * L.outp[l] + o] = b;
+      L.Wf[l][frag_index(o, k, L.inp[l])] = b;
+    }
+}
+
+// The step record moves to the next batch (last node of a training step).
+__global__ void k_step_next(TrainStep* ts) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ts->step += 1;
 }
 
 // BF16 working copies of a layer's weights from the FP32 master [out][in]:
-// W [out_pad][in_pad] and Wt [in_pad][out_pad], zero padded.
+// W [out_pad][in_pad], Wt [in_pad][out_pad] and the fragment-ordered Wf,
+// zero padded.
 __global__ void k_pack(const float* __restrict__ master, int out, int in, int out_pad, int in_pad, __bf16* W,
-                       __bf16* Wt) {
+                       __bf16* Wt, __bf16* Wf) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= out_pad * in_pad) return;
   const int o = i / in_pad, k = i % in_pad;
@@ -233,110 +345,154 @@ __global__ void k_pack(const float* __restrict__ master, int out, int in, int ou
   const __bf16 b = to_bf16(x);
   W[(size_t)o * in_pad + k] = b;
   Wt[(size_t)k * out_pad + o] = b;
+  Wf[frag_index(o, k, in_pad)] = b;
 }
 
-// Fused inference for width 256: a block carries 128 samples through the
-// four layers, their activations kept in LDS as BF16 between layers (rows
-// padded by 8 elements, so the 16 rows of a half-wave's A-fragment reads
-// fall on distinct banks).  Wave w computes output columns 64w .. 64w+63
-// of all 128 rows: per k step it loads its two weight fragments once (each
-// weight is read once per block, not once per wave) and four activation
-// fragments from LDS, for eight 32 x 32 MFMA tiles.  The k order, the MFMA
-// instruction and the epilogues are those of the per-layer kernels, so the
-// outputs are the same bit for bit.
-constexpr int kInferRows = 128;
+// Fused inference for width 256: a block carries 64 samples through the
+// four layers with their BF16 activations in LDS, in two buffers (a layer
+// reads one and writes the other, so one barrier per layer suffices; rows
+// padded by 8 elements): 67.6 KB, so two blocks share a CU and each SIMD
+// runs two waves, one's matrix products overlapping the other's GELU.  The
+// matrix cores compute C^T = W X^T: operand A is a weight fragment (rows =
+// output features), operand B an activation fragment (rows = samples), so
+// a lane's accumulator holds four consecutive features of one sample
+// (elements 4q .. 4q + 3 are features 8q + 4 (lane / 32) + 0..3 of the
+// tile, sample lane % 32), which GELU turns into one 8-byte LDS store.
+// The accumulators start at the bias, as in the per-layer kernels, whose
+// outputs these are bit for bit.  Wave w owns features 64w .. 64w + 63 of
+// every layer and holds their weights in registers for both 32-sample
+// tiles; the GELU of the first tile has the products of the second to
+// overlap with.
+constexpr int kInferRows = 64;
 constexpr int kInferW = 256;
 constexpr int kInferLd = kInferW + 8;
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-// acc[rt][c]: rows 32 rt .. 32 rt + 31, columns 32 (2w + c) .. + 31; column
-// tiles at or beyond ntiles (the padded output layer) are skipped.
-template <int K>
-__device__ __forceinline__ void infer_layer(const __bf16* act, const __bf16* __restrict__ Wl, int ntiles,
-                                            f32x16 (&acc)[4][2]) {
-  const int lane = threadIdx.x & 63, r = lane & 31, kh = (lane >> 5) * 8, w = threadIdx.x >> 6;
+__device__ __forceinline__ void bias_init(f32x16& acc, const float* __restrict__ b) {
+  const int h4 = 4 * ((threadIdx.x & 63) >> 5);
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[rt][c][e] = 0.0f;
-  if (2 * w >= ntiles) return;
-#pragma unroll 2
-  for (int k = 0; k < K; k += 16) {
-    bf16x8 b[2];
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-      if (2 * w + c < ntiles) b[c] = *reinterpret_cast<const bf16x8*>(Wl + (size_t)(32 * (2 * w + c) + r) * K + k + kh);
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(act + (32 * rt + r) * kInferLd + k + kh);
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-        if (2 * w + c < ntiles) acc[rt][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[c], acc[rt][c], 0, 0, 0);
-    }
+  for (int q = 0; q < 4; ++q) {
+    const float4 v = *reinterpret_cast<const float4*>(b + 8 * q + h4);
+    acc[4 * q + 0] = v.x; acc[4 * q + 1] = v.y; acc[4 * q + 2] = v.z; acc[4 * q + 3] = v.w;
   }
 }
 
-__device__ __forceinline__ void infer_hidden_epilogue(__bf16* act, const float* __restrict__ bias,
-                                                      const f32x16 (&acc)[4][2]) {
-  const int lane = threadIdx.x & 63, r = lane & 31, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int col = 32 * (2 * w + c) + r;
-    const float b = bias[col];
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = 32 * rt + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        act[row * kInferLd + col] = to_bf16(gelu(acc[rt][c][e] + b));
-      }
-  }
-}
-
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mlp_infer256(const float* __restrict__ x, int n, int n_in,
-                                                      const float* __restrict__ lohi, const __bf16* __restrict__ W1,
-                                                      const float* __restrict__ b1, const __bf16* __restrict__ W2,
-                                                      const float* __restrict__ b2, const __bf16* __restrict__ W3,
-                                                      const float* __restrict__ b3, const __bf16* __restrict__ W4,
-                                                      const float* __restrict__ b4, float y_scale,
-                                                      float* __restrict__ y) {
-  __shared__ __bf16 act[kInferRows * kInferLd];
+// This wave's weight fragments of a layer with K = 16 KS inputs, k steps
+// K0 .. K1 - 1, from the fragment-ordered copy Wf: output tiles 2w + ft
+// (features 64w + 32 ft ..), one 1 KB wave load each.
+// With OUT set, the layer is the output layer (one 32-row tile, shared by
+// all waves) and only feature tile 0 is loaded.
+template <int KS, int K0 = 0, int K1 = KS, bool OUT = false>
+__device__ __forceinline__ void load_weights(bf16x8 (&wf)[16][2], const __bf16* __restrict__ Wf) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t g0 = (int64_t)blockIdx.x * kInferRows;   // global row of the block's first row
-  {   // scaled inputs in columns 0..15 (zero beyond n_in and beyond n); wave w fills rows 32w ..
-    const int row = 32 * w + (lane & 31), j0 = (lane >> 5) * 8;
-    const int64_t gi = g0 + row;
 #pragma unroll
-    for (int j = j0; j < j0 + 8; ++j) {
-      float v = 0.0f;
-      if (gi < n && j < n_in) v = 2.0f * (x[gi * n_in + j] - lohi[j]) / (lohi[32 + j] - lohi[j]) - 1.0f;
-      act[row * kInferLd + j] = to_bf16(v);
+  for (int k = K0; k < K1; ++k)
+#pragma unroll
+    for (int ft = 0; ft < (OUT ? 1 : 2); ++ft)
+      wf[k][ft] = *reinterpret_cast<const bf16x8*>(Wf + ((size_t)((OUT ? 0 : 2 * w + ft) * KS + k) * 64 + lane) * 8);
+}
+
+// GELU of accumulator elements 4q .. 4q + 3 of one tile into the lane's
+// sample row (dst: that row at the tile's first feature + 4 (lane / 32)).
+__device__ __forceinline__ void gelu_quad(const f32x16& acc, int q, __bf16* dst) {
+  bf16x4 v;
+  v[0] = to_bf16(gelu(acc[4 * q + 0]));
+  v[1] = to_bf16(gelu(acc[4 * q + 1]));
+  v[2] = to_bf16(gelu(acc[4 * q + 2]));
+  v[3] = to_bf16(gelu(acc[4 * q + 3]));
+  *reinterpret_cast<bf16x4*>(dst + 8 * q) = v;
+}
+
+// One hidden layer (K = 16 KS inputs, 256 outputs) for the block's 64
+// samples: out = gelu(b + W in).  The products of sample tile 1 are
+// written interleaved with the GELU of tile 0 (one quad of one feature
+// tile per k step), so the matrix cores and the vector unit of a wave
+// work at the same time; the next layer's weights are loaded into the
+// weight registers once this layer's products are issued, half before
+// and half after the GELU of tile 1.
+template <int KS, int KSN, bool NEXT_OUT = false>
+__device__ __forceinline__ void hidden_layer(const __bf16* in, __bf16* out, bf16x8 (&wf)[16][2],
+                                             const float* __restrict__ bl, const __bf16* __restrict__ Wnext) {
+  const int lane = threadIdx.x & 63, r = lane & 31, kh = (lane >> 5) * 8, w = threadIdx.x >> 6;
+  const int h4 = 4 * (lane >> 5);
+  f32x16 acc[2][2];   // [sample tile][feature tile]
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int ft = 0; ft < 2; ++ft) bias_init(acc[st][ft], bl + 64 * w + 32 * ft);
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const bf16x8 b = *reinterpret_cast<const bf16x8*>(in + r * kInferLd + 16 * k + kh);
+#pragma unroll
+    for (int ft = 0; ft < 2; ++ft)
+      acc[0][ft] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[k][ft], b, acc[0][ft], 0, 0, 0);
+  }
+  __bf16* o0 = out + r * kInferLd + 64 * w + h4;
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const bf16x8 b = *reinterpret_cast<const bf16x8*>(in + (32 + r) * kInferLd + 16 * k + kh);
+#pragma unroll
+    for (int ft = 0; ft < 2; ++ft)
+      acc[1][ft] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[k][ft], b, acc[1][ft], 0, 0, 0);
+    if (KS == 16 && k < 8) gelu_quad(acc[0][k >> 2], k & 3, o0 + 32 * (k >> 2));
+  }
+  if (KS != 16) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) gelu_quad(acc[0][i >> 2], i & 3, o0 + 32 * (i >> 2));
+  }
+  load_weights<KSN, 0, KSN / 2, NEXT_OUT>(wf, Wnext);
+  __bf16* o1 = out + (32 + r) * kInferLd + 64 * w + h4;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) gelu_quad(acc[1][i >> 2], i & 3, o1 + 32 * (i >> 2));
+  load_weights<KSN, KSN / 2, KSN, NEXT_OUT>(wf, Wnext);
+}
+
+// A layer's weight loads are issued around the previous layer's GELU (the
+// weight registers are free once its products are issued), so their
+// latency is hidden behind the GELU and the barrier.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_infer256(
+    const float* __restrict__ x, int n, int n_in, const float* __restrict__ lohi, const __bf16* __restrict__ W1,
+    const float* __restrict__ b1, const __bf16* __restrict__ W2, const float* __restrict__ b2,
+    const __bf16* __restrict__ W3, const float* __restrict__ b3, const __bf16* __restrict__ W4,
+    const float* __restrict__ b4, float y_scale, float* __restrict__ y) {
+  __shared__ __bf16 act[2][kInferRows * kInferLd];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 31, kh = (lane >> 5) * 8;
+  const int64_t g0 = (int64_t)blockIdx.x * kInferRows;   // global row of the block's first row
+  bf16x8 wf[16][2];
+  load_weights<1>(wf, W1);
+  {   // scaled inputs in columns 0..15 (zero beyond n_in and beyond n): thread t fills row t/4, columns 4 (t%4) ..
+    const int row = threadIdx.x >> 2, j0 = 4 * (threadIdx.x & 3);
+    const int64_t gi = g0 + row;
+    bf16x4 v;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float t = 0.0f;
+      if (gi < n && j0 + j < n_in)
+        t = 2.0f * (x[gi * n_in + j0 + j] - lohi[j0 + j]) / (lohi[32 + j0 + j] - lohi[j0 + j]) - 1.0f;
+      v[j] = to_bf16(t);
     }
+    *reinterpret_cast<bf16x4*>(&act[0][row * kInferLd + j0]) = v;
   }
   __syncthreads();
-  f32x16 acc[4][2];
-  infer_layer<16>(act, W1, 8, acc);
+  hidden_layer<1, 16>(act[0], act[1], wf, b1, W2);
   __syncthreads();
-  infer_hidden_epilogue(act, b1, acc);
+  hidden_layer<16, 16>(act[1], act[0], wf, b2, W3);
   __syncthreads();
-  infer_layer<kInferW>(act, W2, 8, acc);
+  // the output layer's fragments (W4: one 32-row tile, 16 k steps) are
+  // loaded as feature tile 0 of every wave
+  hidden_layer<16, 16, true>(act[0], act[1], wf, b3, W4);
   __syncthreads();
-  infer_hidden_epilogue(act, b2, acc);
-  __syncthreads();
-  infer_layer<kInferW>(act, W3, 8, acc);
-  __syncthreads();
-  infer_hidden_epilogue(act, b3, acc);
-  __syncthreads();
-  infer_layer<kInferW>(act, W4, 1, acc);   // output layer: rows of W4 padded to 32, column 0 real (wave 0)
-  if (w == 0 && (lane & 31) == 0) {
+  if (w < 2) {   // waves 0 and 1: samples 32w .. 32w + 31; feature 0 is element 0 of lanes 0..31
+    f32x16 out;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+    for (int e = 0; e < 16; ++e) out[e] = 0.0f;
+    if (lane < 32) out[0] = b4[0];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = 32 * rt + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        if (g0 + row < n) y[g0 + row] = (acc[rt][0][e] + b4[0]) * y_scale;
-      }
+    for (int k = 0; k < 16; ++k) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&act[1][(32 * w + r) * kInferLd + 16 * k + kh]);
+      out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[k][0], b, out, 0, 0, 0);
+    }
+    if (lane < 32 && g0 + 32 * w + r < n) y[g0 + 32 * w + r] = out[0] * y_scale;
   }
 }
 
@@ -363,14 +519,15 @@ hipError_t mlp_gemm_back_hidden(int M, int N, int K, const __bf16* A, int lda, c
   return gemm(M, N, K, A, lda, Bt, ldb, 1, EpiBackHidden{Z, N, dZ, N, dZt, M}, s);
 }
 hipError_t mlp_scale_inputs(const float* x, int n, int n_in, const float* lo, const float* hi, int B, __bf16* X,
-                            __bf16* Xt, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_inputs, dim3((B + 255) / 256), dim3(256), 0, s, x, n, n_in, lo, hi, B, X, Xt);
+                            __bf16* Xt, const TrainStep* ts, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_inputs, dim3((B + 255) / 256), dim3(256), 0, s, x, n, n_in, lo, hi, B, X, Xt, ts);
   return hipGetLastError();
 }
 hipError_t mlp_loss(const float* yhat, const float* t, int n, int B, float inv_scale, float grad_scale, __bf16* dZ,
-                    __bf16* dZt, double* part, double* acc, hipStream_t s) {
+                    __bf16* dZt, double* part, double* acc, const TrainStep* ts, hipStream_t s) {
   const int blocks = (B + 255) / 256;
-  hipLaunchKernelGGL(k_loss, dim3(blocks), dim3(256), 0, s, yhat, t, n, B, inv_scale, grad_scale, dZ, dZt, part);
+  hipLaunchKernelGGL(k_loss, dim3(blocks), dim3(256), 0, s, yhat, t, n, B, inv_scale, grad_scale, dZ, dZt, part,
+                     ts);
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part, blocks, acc);
   return hipGetLastError();
 }
@@ -382,12 +539,18 @@ hipError_t mlp_reduce_splits(const float* partial, int splits, size_t zstride, i
   return hipGetLastError();
 }
 hipError_t mlp_rowsum(const __bf16* dZt, int B, int rows, float* g, hipStream_t s) {
-  hipLaunchKernelGGL(k_rowsum, dim3(rows), dim3(256), 0, s, dZt, B, rows, g);
+  if (B % 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_rowsum, dim3((rows + 3) / 4), dim3(256), 0, s, dZt, B, rows, g);
   return hipGetLastError();
 }
-hipError_t mlp_adam(float* w, float* m, float* v, const float* g, int n, float lr, float b1, float b2, float eps,
-                    float c1, float c2, hipStream_t s) {
-  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps, c1, c2);
+hipError_t mlp_adam_pack(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
+                         float eps, float c1, float c2, const MlpLayers& L, const TrainStep* ts, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps,
+                     c1, c2, L, ts);
+  return hipGetLastError();
+}
+hipError_t mlp_step_next(TrainStep* ts, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_next, dim3(1), dim3(64), 0, s, ts);
   return hipGetLastError();
 }
 hipError_t mlp_infer256(const float* x, int n, int n_in, const float* lohi, const __bf16* W1, const float* b1,
@@ -399,9 +562,10 @@ hipError_t mlp_infer256(const float* x, int n, int n_in, const float* lohi, cons
   return hipGetLastError();
 }
 hipError_t mlp_pack(const float* master, int out, int in, int out_pad, int in_pad, __bf16* W, __bf16* Wt,
-                    hipStream_t s) {
+                    __bf16* Wf, hipStream_t s) {
+  if (out_pad % 32 || in_pad % 16) return hipErrorInvalidValue;
   const int n = out_pad * in_pad;
-  hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, s, master, out, in, out_pad, in_pad, W, Wt);
+  hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, s, master, out, in, out_pad, in_pad, W, Wt, Wf);
   return hipGetLastError();
 }
 

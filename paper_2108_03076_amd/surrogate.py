@@ -108,7 +108,13 @@ def errors(pred, ref):
 
 
 def timed_infer(sur: Surrogate, x, reps=20):
-    """Mean device time (ms) of one inference over the rows of x."""
+    """Inference over the rows of x, timed three ways (ms per call): calls
+    issued back to back (the call is stream-ordered, so this is the rate a
+    serving loop sees), the device time between events bracketing single
+    calls on the context's stream (torch's current stream, which the
+    surrogate launches on), and a call followed by a synchronization (the
+    latency of one isolated request).  Returns (pipelined, device,
+    synchronous, predictions)."""
     import torch
     y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
     sur.infer(x, y)
@@ -117,7 +123,22 @@ def timed_infer(sur: Surrogate, x, reps=20):
     for _ in range(reps):
         sur.infer(x, y)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / reps * 1e3, y
+    pipelined = (time.perf_counter() - t0) / reps * 1e3
+    dev = 0.0
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        sur.infer(x, y)
+        b.record()
+        b.synchronize()
+        dev += a.elapsed_time(b)
+    sync = 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        sur.infer(x, y)
+        torch.cuda.synchronize()
+        sync += time.perf_counter() - t0
+    return pipelined, dev / reps, sync / reps * 1e3, y
 
 
 __all__ = ["box_bounds", "equicorr", "family_batch", "price_with_fallback", "mc_prices", "train", "errors", "timed_infer", "Context", "Surrogate"]

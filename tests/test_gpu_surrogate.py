@@ -148,6 +148,10 @@ def test_save_load_round_trip(tmp_path):
     bad.write_bytes(raw[:-4])
     with pytest.raises(P.PmcError):
         P.Surrogate.load(ctx(), bad)
+    old = tmp_path / "format1.pmcmlp"   # a network of the erf-GELU format
+    old.write_bytes(raw[:6] + b"1" + raw[7:])
+    with pytest.raises(P.PmcError):
+        P.Surrogate.load(ctx(), old)
 
 
 def test_adam_steps_and_cosine_schedule_match_oracle():
@@ -176,6 +180,34 @@ def test_adam_steps_and_cosine_schedule_match_oracle():
         assert err.max() <= 1e-6, (t, err.max())
         assert np.count_nonzero(got != w) > 0.99 * w.size
         w = got
+
+
+def test_graph_training_steps_equal_eager_launches():
+    """Training steps replayed from the captured graph give the same master
+    weights, BF16 copies (through inference) and losses, bit for bit, as
+    the same kernels launched one by one: over several passes whose input
+    tensors move between passes, with other device work and
+    synchronisations between the replays, and across a change of batch size
+    (a new capture)."""
+    g_net, e_net = _net(seed=13), _net(seed=13)
+    x, y = _data(4096, 14)
+    xq = torch.tensor(_data(512, 15)[0], dtype=torch.float32, device="cuda")
+    total = 40
+    for epoch, batch in enumerate((512, 512, 512, 1024, 512)):
+        perm = np.random.default_rng(epoch).permutation(4096)
+        xt = torch.tensor(x[perm], dtype=torch.float32, device="cuda")
+        yt = torch.tensor(y[perm], dtype=torch.float32, device="cuda")
+        lg = g_net.train_epoch(xt, yt, batch=batch, lr_max=2e-3, lr_min=1e-5, total_steps=total)
+        le = e_net.train_epoch(xt, yt, batch=batch, lr_max=2e-3, lr_min=1e-5, total_steps=total, eager=True)
+        assert lg == le, (epoch, lg, le)
+        assert np.array_equal(g_net.get_params(), e_net.get_params()), epoch
+        a = torch.empty(512, dtype=torch.float32, device="cuda")
+        b = torch.empty(512, dtype=torch.float32, device="cuda")
+        g_net.infer(xq, a)
+        e_net.infer(xq, b)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), epoch
+        print(f"[graph] pass {epoch} batch {batch}: loss {lg:.6e}", flush=True)
 
 
 def _c5_payoff():
