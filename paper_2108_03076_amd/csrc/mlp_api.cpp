@@ -55,7 +55,7 @@ struct pmc_mlp {
   Buf px, py;   // surrogate pricing: the in-box points and their predictions
   int64_t gen = 0;   // bumped whenever a work buffer moves (a captured step is then stale)
   // one training step captured as a graph (batch size B_graph, buffers of generation gen_graph)
-  Buf tstep, hyper;
+  Buf tstep, hyper, part_epoch;   // the step record, per-step hyper-parameters, per-step loss partials
   std::vector<float> hyper_host;
   TrainStep tstep_host{};
   hipGraphExec_t step_exec = nullptr;
@@ -146,35 +146,37 @@ int forward(pmc_mlp* M, const float* x, int n, int B, bool train, const TrainSte
 }
 
 // Loss and gradients (into M->grad) of mean((yhat - y/y_scale)^2) over n
-// rows (targets y, or with ts the step record's batch); adds the batch's sum
-// of squared errors to loss_acc.
-int backward(pmc_mlp* M, const float* y, int n, int B, const TrainStep* ts = nullptr) {
+// rows.  Without a step record: targets y, and the batch's sum of squared
+// errors is added to loss_acc.  With one (a training step): its batch, the
+// loss partials go to the pass's slots (part_epoch), and the last gradient
+// launch advances the record.
+int backward(pmc_mlp* M, const float* y, int n, int B, TrainStep* ts = nullptr) {
   hipStream_t s = stream_of(M);
   const int W = M->width;
   float* g = M->grad.as<float>();
   MLP_TRY(M, mlp_loss(M->Y.as<float>(), y, n, B, (float)(1.0 / M->y_scale), 2.0f / (float)n,
-                      M->dZ4.as<__bf16>(), M->dZ4t.as<__bf16>(), M->part_loss.as<double>(),
-                      M->loss_acc.as<double>(), ts, s));
+                      M->dZ4.as<__bf16>(), M->dZ4t.as<__bf16>(),
+                      ts ? M->part_epoch.as<double>() : M->part_loss.as<double>(), M->loss_acc.as<double>(), ts, s));
   float* part = M->partial.as<float>();
   // layer 4: dW4 = dZ4^T H3, db4, dZ3 = (dZ4 W4) * gelu'(Z3)
   MLP_TRY(M, mlp_gemm_f32(32, W, B, M->dZ4t.as<__bf16>(), B, M->Ht[2].as<__bf16>(), B, kSplits, part, W, s));
-  MLP_TRY(M, mlp_reduce_splits(part, kSplits, (size_t)32 * W, W, 1, W, g + M->oW[3], s));
-  MLP_TRY(M, mlp_rowsum(M->dZ4t.as<__bf16>(), B, 1, g + M->ob[3], s));
+  MLP_TRY(M, mlp_layer_grads(part, kSplits, (size_t)32 * W, W, 1, W, g + M->oW[3], M->dZ4t.as<__bf16>(), B, 1,
+                             g + M->ob[3], nullptr, s));
   MLP_TRY(M, mlp_gemm_back_hidden(B, W, 32, M->dZ4.as<__bf16>(), 32, M->Wt[3].as<__bf16>(), 32,
                                   M->Z[2].as<float>(), M->dZ[2].as<__bf16>(), M->dZt[2].as<__bf16>(), s));
   // layers 3 and 2
   for (int l = 2; l >= 1; --l) {
     MLP_TRY(M, mlp_gemm_f32(W, W, B, M->dZt[l].as<__bf16>(), B, M->Ht[l - 1].as<__bf16>(), B, kSplits, part, W, s));
-    MLP_TRY(M, mlp_reduce_splits(part, kSplits, (size_t)W * W, W, W, W, g + M->oW[l], s));
-    MLP_TRY(M, mlp_rowsum(M->dZt[l].as<__bf16>(), B, W, g + M->ob[l], s));
+    MLP_TRY(M, mlp_layer_grads(part, kSplits, (size_t)W * W, W, W, W, g + M->oW[l], M->dZt[l].as<__bf16>(), B, W,
+                               g + M->ob[l], nullptr, s));
     MLP_TRY(M, mlp_gemm_back_hidden(B, W, W, M->dZ[l].as<__bf16>(), W, M->Wt[l].as<__bf16>(), W,
                                     M->Z[l - 1].as<float>(), M->dZ[l - 1].as<__bf16>(),
                                     M->dZt[l - 1].as<__bf16>(), s));
   }
   // layer 1: dW1 = dZ1^T X (X^T has 32 padded rows), db1
   MLP_TRY(M, mlp_gemm_f32(W, 32, B, M->dZt[0].as<__bf16>(), B, M->Xt.as<__bf16>(), B, kSplits, part, 32, s));
-  MLP_TRY(M, mlp_reduce_splits(part, kSplits, (size_t)W * 32, 32, W, M->n_in, g + M->oW[0], s));
-  MLP_TRY(M, mlp_rowsum(M->dZt[0].as<__bf16>(), B, W, g + M->ob[0], s));
+  MLP_TRY(M, mlp_layer_grads(part, kSplits, (size_t)W * 32, 32, W, M->n_in, g + M->oW[0], M->dZt[0].as<__bf16>(), B,
+                             W, g + M->ob[0], ts, s));
   return PMC_OK;
 }
 
@@ -349,7 +351,8 @@ void step_hyper(const pmc_train_opts* o, int64_t step, float out[3]) {
 }
 
 // One training step over batch ts->step of the step record: forward, loss
-// and gradients, Adam with the BF16 repack, then the record's next step.
+// and gradients (whose last launch advances the record), then Adam with
+// the BF16 repack.
 int enqueue_step(pmc_mlp* M, const pmc_train_opts* o, int B, TrainStep* ts) {
   int rc = forward(M, nullptr, B, B, true, ts);
   if (rc == PMC_OK) rc = backward(M, nullptr, B, B, ts);
@@ -358,7 +361,6 @@ int enqueue_step(pmc_mlp* M, const pmc_train_opts* o, int B, TrainStep* ts) {
   MLP_TRY(M, mlp_adam_pack(M->master.as<float>(), M->m.as<float>(), M->v.as<float>(), M->grad.as<float>(),
                            M->n_params, 0.0f, (float)o->beta1, (float)o->beta2, (float)o->eps, 1.0f, 1.0f,
                            M->layers(), ts, s));
-  MLP_TRY(M, mlp_step_next(ts, s));
   return PMC_OK;
 }
 
@@ -419,6 +421,11 @@ extern "C" int pmc_mlp_train_epoch(pmc_mlp* m, const float* x, const float* y, i
   MLP_TRY(m, hipSetDevice(ctx_device(m->ctx)));
   MLP_TRY(m, m->tstep.ensure(sizeof(TrainStep)));
   MLP_TRY(m, m->hyper.ensure((size_t)steps * 3 * sizeof(float)));
+  const int64_t n_part = steps * ((B + 255) / 256);   // loss partials: one per step and loss block
+  if ((size_t)n_part * sizeof(double) > m->part_epoch.cap) {
+    MLP_TRY(m, m->part_epoch.ensure((size_t)n_part * sizeof(double)));
+    m->gen++;   // a captured step writes its partials there
+  }
   // the previous epoch's uploads must be done before their host copies change
   MLP_TRY(m, hipStreamSynchronize(s));
   m->hyper_host.resize((size_t)steps * 3);
@@ -438,6 +445,7 @@ extern "C" int pmc_mlp_train_epoch(pmc_mlp* m, const float* x, const float* y, i
     if (rc != PMC_OK) return rc;
     for (int64_t k = 0; k < steps; ++k) MLP_TRY(m, hipGraphLaunch(m->step_exec, s));
   }
+  MLP_TRY(m, mlp_sum_parts(m->part_epoch.as<double>(), n_part, m->loss_acc.as<double>(), s));
   m->step += steps;
   double acc = 0;
   MLP_TRY(m, hipMemcpyAsync(&acc, m->loss_acc.p, 8, hipMemcpyDeviceToHost, s));

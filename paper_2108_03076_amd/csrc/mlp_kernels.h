@@ -45,16 +45,23 @@ hipError_t mlp_gemm_back_hidden(int M, int N, int K, const __bf16* A, int lda, c
 hipError_t mlp_scale_inputs(const float* x, int n, int n_in, const float* lo, const float* hi, int B, __bf16* X,
                             __bf16* Xt, const TrainStep* ts, hipStream_t s);
 // t targets [n] (or, with ts, the step record's batch).
+// Loss partials and the output layer's gradient dZ (and dZ^T) from yhat
+// and the targets t [n] (or, with ts, the step record's batch).  Without a
+// step record the batch's squared errors are added to acc; with one, each
+// block's partial goes to part[step * blocks + block] and mlp_sum_parts
+// adds a whole pass's partials at its end.
 hipError_t mlp_loss(const float* yhat, const float* t, int n, int B, float inv_scale, float grad_scale, __bf16* dZ,
                     __bf16* dZt, double* part, double* acc, const TrainStep* ts, hipStream_t s);
-hipError_t mlp_reduce_splits(const float* partial, int splits, size_t zstride, int ldp, int rows, int cols,
-                             float* g, hipStream_t s);
-hipError_t mlp_rowsum(const __bf16* dZt, int B, int rows, float* g, hipStream_t s);
+hipError_t mlp_sum_parts(const double* part, int64_t n, double* acc, hipStream_t s);
+// One layer's weight gradient g [rows][cols] from its 16 split-K partials
+// and bias gradient gb [rows_b] (row sums of dZt [rows_b][B]) in one
+// launch; with ts_next, the launch also advances the step record.
+hipError_t mlp_layer_grads(const float* partial, int splits, size_t zstride, int ldp, int rows, int cols, float* g,
+                           const __bf16* dZt, int B, int rows_b, float* gb, TrainStep* ts_next, hipStream_t s);
 // Adam on the FP32 master parameters and the BF16 repack of the weights
 // (with ts: lr, c1, c2 from its current step).
 hipError_t mlp_adam_pack(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
                          float eps, float c1, float c2, const MlpLayers& L, const TrainStep* ts, hipStream_t s);
-hipError_t mlp_step_next(TrainStep* ts, hipStream_t s);
 // W [out_pad][in_pad], Wt [in_pad][out_pad] and the fragment-ordered Wf
 // (A-operand fragments of 32-row output tiles and 16-wide k steps, each
 // 64 lanes x 16 bytes, tile-major) from the FP32 master weights.

@@ -251,7 +251,8 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ yhat, co
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  // with a step record: one slot per (step, block), summed once per pass
+  if (threadIdx.x == 0) part[(ts ? ts->step * (int64_t)gridDim.x : 0) + blockIdx.x] = red[0];
 }
 
 // out[0] += sum of part[0..n) in a fixed order (one thread).
@@ -262,51 +263,63 @@ __global__ void k_sum_parts(const double* part, int n, double* out) {
   out[0] += s;
 }
 
-// g[row][col] (rows < rows_real, cols < cols_real, row-major ld cols_real)
-// = sum over z of partial[z][row][col] (ld ldp), fixed order.
-__global__ void k_reduce_splits(const float* __restrict__ partial, int splits, size_t zstride, int ldp,
-                                int rows_real, int cols_real, float* __restrict__ g) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= rows_real * cols_real) return;
-  const int row = i / cols_real, col = i % cols_real;
-  float s = 0.0f;
-  for (int z = 0; z < splits; ++z) s += partial[z * zstride + (size_t)row * ldp + col];
-  g[i] = s;
-}
-
-// g[r] = sum over b of dZt[r][b] (BF16) in a fixed order: one wave per row,
-// lane l sums elements 8 (l + 64 i) .. + 7 for i = 0, 1, .. (16-byte loads),
-// then the lanes' sums are added pairwise by a butterfly.  B a multiple of
-// 8.
-__global__ __launch_bounds__(256) void k_rowsum(const __bf16* __restrict__ dZt, int B, int rows_real,
-                                                float* __restrict__ g) {
+// The weight and bias gradients of one layer in one launch.  Blocks
+// [0, n_red) reduce the split-K partials: g[row][col] (rows < rows_real,
+// cols < cols_real, row-major with ld cols_real) = the sum over the SPLITS
+// partials partial[z][row][col] (ld ldp) in z order.  The other blocks sum
+// rows of dZt (BF16 [rows_b][B]) into gb, one wave per row: lane l sums
+// elements 8 (l + 64 i) .. + 7 for i = 0, 1, .. (16-byte loads, B a multiple
+// of 8), then the lanes' sums are added by a butterfly.  With a step
+// record, block 0 also advances it: this launch is the last of a step's
+// gradients, and nothing in it reads the record.
+template <int SPLITS>
+__global__ __launch_bounds__(256) void k_layer_grads(const float* __restrict__ partial, size_t zstride, int ldp,
+                                                     int rows_real, int cols_real, float* __restrict__ g,
+                                                     const __bf16* __restrict__ dZt, int B, int rows_b,
+                                                     float* __restrict__ gb, int n_red, TrainStep* ts_next) {
+  if (ts_next && blockIdx.x == 0 && threadIdx.x == 0) ts_next->step += 1;
+  if ((int)blockIdx.x < n_red) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows_real * cols_real) return;
+    const int row = i / cols_real, col = i % cols_real;
+    const float* p = partial + (size_t)row * ldp + col;
+    float v[SPLITS];
+#pragma unroll
+    for (int z = 0; z < SPLITS; ++z) v[z] = p[z * zstride];
+    float sum = 0.0f;
+#pragma unroll
+    for (int z = 0; z < SPLITS; ++z) sum += v[z];
+    g[i] = sum;
+    return;
+  }
   const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= rows_real) return;
+  const int r = ((int)blockIdx.x - n_red) * 4 + (threadIdx.x >> 6);
+  if (r >= rows_b) return;
   const __bf16* p = dZt + (size_t)r * B;
-  float s = 0.0f;
+  float sum = 0.0f;
   for (int b = 8 * lane; b < B; b += 512) {
     const bf16x8 v = *reinterpret_cast<const bf16x8*>(p + b);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) s += from_bf16(v[j]);
+    for (int j = 0; j < 8; ++j) sum += from_bf16(v[j]);
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) g[r] = s;
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+  if (lane == 0) gb[r] = sum;
 }
 
 // One Adam step on the FP32 master parameters followed by the BF16 copies
-// W [out_pad][in_pad] and Wt [in_pad][out_pad] of each updated weight (the
-// zero padding is written once, at creation).  With a step record, the
-// learning rate and the bias corrections are its entries for the current
-// step.
+// W [out_pad][in_pad], Wt [in_pad][out_pad] and Wf (fragment order) of
+// each updated weight (the zero padding is written once, at creation).
+// With a step record, the learning rate and the bias corrections are its
+// entries for the step whose gradients these are: the gradient launch has
+// already advanced the record, so that step is step - 1.
 __global__ void k_adam_pack(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
                             const float* __restrict__ g, int64_t n, float lr, float b1, float b2, float eps,
                             float c1, float c2, MlpLayers L, const TrainStep* __restrict__ ts) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (ts) {
-    const float* h = ts->hyper + 3 * ts->step;
+    const float* h = ts->hyper + 3 * (ts->step - 1);
     lr = h[0]; c1 = h[1]; c2 = h[2];
   }
   const float gi = g[i];
@@ -326,11 +339,6 @@ __global__ void k_adam_pack(float* __restrict__ w, float* __restrict__ m, float*
       L.Wt[l][(size_t)k * L.outp[l] + o] = b;
       L.Wf[l][frag_index(o, k, L.inp[l])] = b;
     }
-}
-
-// The step record moves to the next batch (last node of a training step).
-__global__ void k_step_next(TrainStep* ts) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) ts->step += 1;
 }
 
 // BF16 working copies of a layer's weights from the FP32 master [out][in]:
@@ -528,29 +536,26 @@ hipError_t mlp_loss(const float* yhat, const float* t, int n, int B, float inv_s
   const int blocks = (B + 255) / 256;
   hipLaunchKernelGGL(k_loss, dim3(blocks), dim3(256), 0, s, yhat, t, n, B, inv_scale, grad_scale, dZ, dZt, part,
                      ts);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part, blocks, acc);
+  if (!ts) hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part, blocks, acc);
   return hipGetLastError();
 }
-hipError_t mlp_reduce_splits(const float* partial, int splits, size_t zstride, int ldp, int rows, int cols,
-                             float* g, hipStream_t s) {
-  const int n = rows * cols;
-  hipLaunchKernelGGL(k_reduce_splits, dim3((n + 255) / 256), dim3(256), 0, s, partial, splits, zstride, ldp, rows,
-                     cols, g);
+hipError_t mlp_sum_parts(const double* part, int64_t n, double* acc, hipStream_t s) {
+  if (n < 1 || n > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part, (int)n, acc);
   return hipGetLastError();
 }
-hipError_t mlp_rowsum(const __bf16* dZt, int B, int rows, float* g, hipStream_t s) {
-  if (B % 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rowsum, dim3((rows + 3) / 4), dim3(256), 0, s, dZt, B, rows, g);
+hipError_t mlp_layer_grads(const float* partial, int splits, size_t zstride, int ldp, int rows, int cols, float* g,
+                           const __bf16* dZt, int B, int rows_b, float* gb, TrainStep* ts_next, hipStream_t s) {
+  if (splits != 16 || B % 8 || rows < 1 || cols < 1 || rows_b < 1) return hipErrorInvalidValue;
+  const int n_red = (rows * cols + 255) / 256;
+  hipLaunchKernelGGL(k_layer_grads<16>, dim3(n_red + (rows_b + 3) / 4), dim3(256), 0, s, partial, zstride, ldp, rows,
+                     cols, g, dZt, B, rows_b, gb, n_red, ts_next);
   return hipGetLastError();
 }
 hipError_t mlp_adam_pack(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
                          float eps, float c1, float c2, const MlpLayers& L, const TrainStep* ts, hipStream_t s) {
   hipLaunchKernelGGL(k_adam_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps,
                      c1, c2, L, ts);
-  return hipGetLastError();
-}
-hipError_t mlp_step_next(TrainStep* ts, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_next, dim3(1), dim3(64), 0, s, ts);
   return hipGetLastError();
 }
 hipError_t mlp_infer256(const float* x, int n, int n_in, const float* lohi, const __bf16* W1, const float* b1,
