@@ -990,6 +990,11 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
   // buffer's alignment allow it: 16 bytes' worth always, and up to 64 bytes
   // while the launch keeps at least one wave per SIMD (2^16 lanes), since the
   // wave-uniform work per slot is shared by more paths.
+  // A fused launch that streams its paths gives each lane two paths once
+  // the launch keeps at least one wave per SIMD (2^16 lanes): the paths
+  // share each read's wave-uniform work (slot lookup, loop control), which
+  // halves the scalar instructions per path-date; every path's payoff is
+  // the same bit for bit.
   int lanes = 1;
   if (mode == PMC_MODE_TWO_PHASE && o->engine != PMC_ENGINE_INTERPRETER && n_slots > 0) {
     const int base_p = 16 / (int)sizeof(T);
@@ -1001,6 +1006,8 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
         break;
       }
     }
+  } else if (mode == PMC_MODE_FUSED && stream && N >= (1u << 17)) {
+    lanes = 2;
   }
   const uint64_t tile_paths = (uint64_t)block * (uint64_t)lanes;
   const uint32_t tiles = (uint32_t)((N + tile_paths - 1) / tile_paths);
@@ -1051,7 +1058,8 @@ int price_one(pmc_ctx* c, const pmc_payoff* p, const int32_t* tenv, const double
     L.factor = 1;
     L.status = status_dev(c, 1);
     EngineLaunch e;
-    st = resolve_engine(c, p, o, prec, false, L, (int)tiles, block, 1, (int64_t)n_slots * A, full, env, e, stream);
+    st = resolve_engine(c, p, o, prec, false, L, (int)tiles, block, lanes, (int64_t)n_slots * A, full, env, e,
+                        stream);
     if (st != PMC_OK) return st;
     if (keyed) {   // the next identical call can reuse all of this
       auto& pr = c->prepared;

@@ -202,6 +202,9 @@ def test_c3_full_size_sampled_paths():
 
 
 FULL_SIZE = {"c3": W.C3, "c1": _small(W.C1, n_paths=1 << 20),
+             # a ragged count: the fused kernel streams two paths per lane
+             # from 2^17 paths, and its last lane holds one real path
+             "c3_odd": _small(W.C3, n_paths=(1 << 17) + 3),
              # three correlated assets: the fused kernel's blocks make the step
              # coefficients from their own factorisation, the path generator
              # from the prepared factor; the paths must still agree bit for bit
@@ -211,8 +214,10 @@ FULL_SIZE = {"c3": W.C3, "c1": _small(W.C1, n_paths=1 << 20),
 @pytest.mark.parametrize("name", list(FULL_SIZE))
 def test_stored_path_evaluator_at_full_size_equals_fused(name):
     """At 2^20 paths the stored-path evaluator gives each lane 16 FP32 (or
-    8 FP64) consecutive paths; every per-path payoff equals the fused
-    kernel's bit for bit (the same path values and the same operations)."""
+    8 FP64) consecutive paths, and the fused kernel streams two paths per
+    lane where the payoff reads forward; every per-path payoff equals the
+    fused kernel's bit for bit (the same path values and the same
+    operations), also at a ragged path count."""
     import paper_2108_03076_amd as P
     cfg = FULL_SIZE[name]
     n = cfg.n_paths
