@@ -136,8 +136,11 @@ void pmc_payoff_free(pmc_payoff* p);
  * query).  pmc_contract_load compiles and loads it as pmc_payoff_load
  * does, with the same label arguments (observables in obs(l, i) are asset
  * or parameter labels; template variables in t are tvar_names).
- * Errors: PMC_E_PARSE (contract syntax, with the offset in
- * pmc_last_error), and those of pmc_payoff_load. */
+ * Times and observation offsets are numerals below 2^31 (days); contracts
+ * and expressions nest at most 1000 deep.
+ * Errors: PMC_E_PARSE (contract syntax, a numeral out of range, nesting
+ * beyond the limit; with the offset in pmc_last_error), and those of
+ * pmc_payoff_load. */
 int pmc_contract_compile(const char* cl_text, size_t len, char* il_out, size_t cap, size_t* il_len);
 int pmc_contract_load(pmc_ctx* ctx, const char* cl_text, size_t len,
                       const char* const* asset_labels, int n_assets,

@@ -139,10 +139,31 @@ void put_te(std::string& o, const TE& t) {
 // A recursive-descent reader that compiles while it reads: tau_e(e, t0)
 // and tau_c(c, t0) are syntax-directed, so each construct's payoff text is
 // produced from its parts' texts with the t0 in force at that point.
+// Times and observation offsets are days: naturals of at most 31 bits (the
+// payoff language's are 32-bit), so sums of nested translations stay far
+// inside 64 bits.
+bool day_numeral(const std::string& s, int64_t& v) {
+  if (s.empty() || s.size() > 10 || s.find_first_not_of("0123456789") != std::string::npos) return false;
+  v = std::strtoll(s.c_str(), nullptr, 10);
+  return v <= 0x7fffffff;
+}
+
+// Nesting of contracts and expressions the compiler follows (it recurses
+// once per level).
+constexpr int kMaxNesting = 1000;
+
 struct Compiler {
   const std::vector<Tok>& tk;
   size_t p = 0;
   std::string err;
+  int depth = 0;
+  // one level deeper for the lifetime of the guard; ok is false beyond the limit
+  struct Deeper {
+    Compiler& c;
+    bool ok;
+    explicit Deeper(Compiler& cc) : c(cc), ok(++cc.depth <= kMaxNesting) {}
+    ~Deeper() { --c.depth; }
+  };
 
   const Tok& cur() const { return tk[p]; }
   bool is(const char* punct) const { return cur().kind == Tok::PUNCT && cur().text == punct; }
@@ -166,9 +187,9 @@ struct Compiler {
   // TExp: a numeral or a template variable
   bool texp(TP& out) {
     if (cur().kind == Tok::NUM) {
-      const std::string& s = cur().text;
-      if (s.find_first_not_of("0123456789") != std::string::npos) return fail("a time must be a natural number");
-      out = nat(std::stoll(s));
+      int64_t v;
+      if (!day_numeral(cur().text, v)) return fail("a time must be a natural number below 2^31");
+      out = nat(v);
       ++p;
       return true;
     }
@@ -185,6 +206,8 @@ struct Compiler {
 
   // --- contracts: tau_c(c, t0)
   bool contract(const TP& t0, std::string& o) {
+    const Deeper d(*this);
+    if (!d.ok) return fail("contract nested too deeply");
     if (cur().kind != Tok::ID) return fail("expected a contract");
     const std::string k = cur().text;
     ++p;
@@ -318,6 +341,8 @@ struct Compiler {
     return true;
   }
   bool unary(const TP& t0, std::string& o) {
+    const Deeper d(*this);
+    if (!d.ok) return fail("expression nested too deeply");
     if (is("-")) {
       ++p;
       std::string x;
@@ -343,6 +368,8 @@ struct Compiler {
     return true;
   }
   bool primary(const TP& t0, std::string& o) {
+    const Deeper d(*this);
+    if (!d.ok) return fail("expression nested too deeply");
     if (is("(")) {
       ++p;
       return expr(t0, o) && expect(")");
@@ -367,9 +394,10 @@ struct Compiler {
       if (!expect("(") || !ident(label) || !expect(",")) return false;
       bool negative = false;
       if (is("-")) { negative = true; ++p; }
-      if (cur().kind != Tok::NUM || cur().text.find_first_not_of("0123456789") != std::string::npos)
-        return fail("an observation offset must be an integer");
-      const int64_t i = std::stoll(cur().text) * (negative ? -1 : 1);
+      int64_t i;
+      if (cur().kind != Tok::NUM || !day_numeral(cur().text, i))
+        return fail("an observation offset must be an integer of at most 31 bits");
+      if (negative) i = -i;
       ++p;
       if (!expect(")")) return false;
       o = "(model " + label + " ";

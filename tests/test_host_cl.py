@@ -129,7 +129,10 @@ def test_malformed_contracts_are_refused():
     import paper_2108_03076_amd as P
     for bad in ("", "scale(1.0 transfer(a, b))", "translate(-1, zero)", "translate(1.5, zero)",
                 "both(zero)", "ifWithin(true, T, zero)", "scale(obs(S, 0.5), zero)", "frobnicate(zero)",
-                "zero zero", "scale(1 = 2, zero)", "all[]", "scale(1.0.0, zero)"):
+                "zero zero", "scale(1 = 2, zero)", "all[]", "scale(1.0.0, zero)",
+                # numerals beyond 31 bits, nesting beyond the limit (refused, never a crash)
+                "translate(99999999999999999999, zero)", "scale(obs(S, 4294967296), zero)",
+                "scale(1.0, " * 1001 + "zero" + ")" * 1001, "scale(" + "-" * 5000 + "1.0, zero)"):
         with pytest.raises(P.PmcError) as e:
             P.compile_contract(bad)
         assert e.value.name == "E_PARSE", bad
