@@ -56,13 +56,13 @@ OPS_IL_DOWN_AND_OUT = 4
 
 # HBM traffic of the headline kernel per launch, from two rocprofv3 --pmc
 # passes (FETCH_SIZE, WRITE_SIZE: KiB per dispatch of the batched
-# down-and-out kernel) scaled by what the same counters read for the 1 GiB
-# device-to-device copies of the same run (FETCH reads 0.5 KiB per KiB
-# copied, WRITE 1.0; profiles/pmc_jit_mc_batched_down_and_out_counters.md).
-# Valid only for the engine sources it was measured on (hash below);
-# otherwise reported as null.
-TRAFFIC = {"engine_sha256": "f062fcd1f06cbb266bc18c63f21bfd62bba984b2fe642c21e2da62fe2b2598ba",
-           "fetch_kib": 14729.0, "write_kib": 6214.1, "fetch_scale": 2.0, "write_scale": 1.0}
+# down-and-out kernel at the tuned tile, mean of the run's two dispatches)
+# scaled by what the same counters read for the 256 MiB device-to-device
+# copies of the same run (FETCH reads 0.5 KiB per KiB copied, WRITE 1.0;
+# profiles/pmc_jit_mc_batched_down_and_out_counters.md).  Valid only for the
+# engine sources it was measured on (hash below); otherwise reported as null.
+TRAFFIC = {"engine_sha256": "00c43e1950fb54bd5aa35be47b0851e244502b3202a3ef68252c1a49cf2d1cc6",
+           "fetch_kib": 18494.3, "write_kib": 6224.7, "fetch_scale": 2.0, "write_scale": 1.0}
 ENGINE_SOURCES = ("paper_2108_03076_amd/csrc/mc_engine.h", "paper_2108_03076_amd/csrc/pmc_device.h",
                   "paper_2108_03076_amd/csrc/codegen.cpp")
 C4_CPU_SAMPLE = (4, 1 << 12)   # oracle baseline: instances, paths each

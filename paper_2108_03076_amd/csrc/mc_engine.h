@@ -191,6 +191,8 @@ using kptr = const __attribute__((address_space(4))) T*;
 template <typename T>
 using lptr = const __attribute__((address_space(3))) T*;
 template <typename T>
+using lwptr = __attribute__((address_space(3))) T*;
+template <typename T>
 __device__ __forceinline__ kptr<T> K(const T* p) { return (kptr<T>)p; }
 
 __device__ __forceinline__ InstDesc load_desc(const InstDesc* base, int i) {
@@ -683,7 +685,7 @@ struct GenSource {
 // sliding window serves the others): each slot is generated once, when it
 // is first read, and only the newest slot's prices are held, so there is no
 // window to fill or index.  The words of a path are consumed in order, four
-// per Philox block, from a buffer that shifts down by one word per use.
+// per Philox block, from a per-thread buffer in LDS read at a uniform index.
 // P paths per lane (P >= 1) share the wave-uniform work of every read and of
 // the payoff's control flow (P = 2 halves the scalar instructions per
 // path-date).  Each path's words, normals, steps and prices are those of
@@ -699,7 +701,13 @@ struct GenStream {
   int last;        // newest generated slot (uniform), -1 before the first
   int left;        // words left in the buffer (uniform)
   uint32_t next_blk;
-  uint32_t b0[P], b1[P], b2[P], b3[P];
+  // The Philox block in use (four words per path) sits in LDS, this
+  // thread's word j of path e at wb[(j * P + e) * bs]: held in registers it
+  // was part of the state every read carries, and the date loop and the
+  // read's step kept that state in two register sets, copying it in and out
+  // at every read.
+  lwptr<uint32_t> wb;
+  int bs;
   uint32_t path, k0, k1, inst;
   kptr<T> slotc;
   kptr<T> histp;
@@ -713,7 +721,10 @@ struct GenStream {
       for (int a = 0; a < A; ++a) x[e][a] = T(0);
     last = -1; left = 0; next_blk = 0;
   }
-  __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p, const T* l_own, bool own) {
+  __device__ __forceinline__ void init(const Args<T>& g, const InstDesc& d, uint32_t p, const T* l_own, bool own,
+                                       lwptr<uint32_t> wbuf) {
+    wb = wbuf + threadIdx.x;
+    bs = (int)blockDim.x;
     path = p;
     k0 = g.k0; k1 = g.k1; inst = d.instance;
     M.load(g, d, l_own, own);
@@ -729,16 +740,15 @@ struct GenStream {
       for (int e = 0; e < P; ++e) {
         uint32_t o[4];
         philox4x32_10(path + (uint32_t)e, next_blk, inst, 0u, k0, k1, o);
-        b0[e] = o[0]; b1[e] = o[1]; b2[e] = o[2]; b3[e] = o[3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wb[(q * P + e) * bs] = o[q];
       }
       ++next_blk;
       left = 4;
     }
+    const int q = 4 - left;
 #pragma unroll
-    for (int e = 0; e < P; ++e) {
-      out[e] = b0[e];
-      b0[e] = b1[e]; b1[e] = b2[e]; b2[e] = b3[e];
-    }
+    for (int e = 0; e < P; ++e) out[e] = wb[(q * P + e) * bs];
     --left;
   }
   // the next slot: GenSource::advance per path, then its prices
@@ -874,8 +884,6 @@ struct MemSource {
 // window lives in LDS laid out [entry][thread] so that a wave reads or
 // writes one contiguous 64 * P * sizeof(T) bytes (no bank conflicts, and no
 // register copies of a loop-carried window).
-template <typename T>
-using lwptr = __attribute__((address_space(3))) T*;
 constexpr int kLdsWin = 4;   // window entries per lane
 
 template <typename T, int A, int P>
@@ -1216,8 +1224,9 @@ __device__ __forceinline__ void mc_body(const Args<T>& g) {
         src.init(g, D, p);
         v = Eval::template run<T>(g, D, src, frames);
       } else if constexpr (STREAM) {
+        __shared__ uint32_t stream_words[4 * P * 256];   // [word][path][thread], blockDim <= 256 (4 KB per path)
         GenStream<T, A, P> src;
-        src.init(g, D, p, l_own, own);
+        src.init(g, D, p, l_own, own, (lwptr<uint32_t>)stream_words);
         v = Eval::template run<T>(g, D, src, frames);
       } else {
         GenSource<T, RNG, A, FULL> src;
