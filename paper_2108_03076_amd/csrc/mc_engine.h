@@ -596,6 +596,42 @@ struct GenSource {
     advance(xw, slotc[2 * q], slotc[2 * q + 1]);
   }
 
+  // Every slot of the path, in order, into the store out[slot][asset][path]
+  // (Philox).  The words are consumed in counter order, so the loop runs over
+  // groups of G slots whose G*A words fill NB whole Philox blocks: each word
+  // comes from its block by a fixed index, with no per-word block test or
+  // selection among the four.  The same words, steps and prices as step().
+  __device__ __forceinline__ void store_philox(T* out, uint32_t npath) {
+    constexpr int G = (A % 4 == 0) ? 1 : (A % 2 == 0) ? 2 : 4;
+    constexpr int NB = G * A / 4;
+    const int S = n_slots;
+    int q = 0;
+    uint32_t b = 0;
+    for (; q + G <= S; q += G, b += NB) {
+      uint32_t w[4 * NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) philox4x32_10(path, b + c, inst, 0u, k0, k1, &w[4 * c]);
+#pragma unroll
+      for (int j = 0; j < G; ++j) store_slot(out, npath, q + j, &w[j * A]);
+    }
+    if (q < S) {
+      uint32_t w[4 * NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) philox4x32_10(path, b + c, inst, 0u, k0, k1, &w[4 * c]);
+#pragma unroll
+      for (int j = 0; j < G - 1; ++j)
+        if (q + j < S) store_slot(out, npath, q + j, &w[j * A]);
+    }
+  }
+  __device__ __forceinline__ void store_slot(T* out, uint32_t npath, int q, const uint32_t* wq) {
+    uint32_t xw[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) xw[a] = wq[a];
+    advance(xw, slotc[2 * q], slotc[2 * q + 1]);
+#pragma unroll
+    for (int a = 0; a < A; ++a) out[((size_t)q * A + a) * npath + path] = price(a);
+  }
+
   // Generates slots up to s + WS - 1 (from the spot again on a backward
   // read) and keeps slots s .. s+WS-1 in the window.
   __device__ __forceinline__ void refill(T (&win)[kWindow], int s) {
@@ -1303,6 +1339,12 @@ __device__ __forceinline__ void pathgen_body(const Args<T>& g, T* out, uint32_t*
   const InstDesc D = load_desc(g.desc, 0);
   GenSource<T, RNG, A> src;
   src.init(g, D, path, lo_tab, has_lo);
+  if constexpr (RNG == 0) {
+    if (!wout && !zout) {
+      src.store_philox(out, n_paths);
+      return;
+    }
+  }
   for (int q = 0; q < D.n_slots; ++q) {
     src.step(q, wout, zout, n_paths);
 #pragma unroll

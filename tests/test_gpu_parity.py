@@ -66,6 +66,48 @@ def test_streams_and_paths(name):
         assert np.max(np.abs(S / oS - 1)) < 2e-5
 
 
+# Philox cases for the path store's block-ordered loop: 1 asset (37 slots: a
+# ragged group; 1 slot: the ragged group alone), 2 assets (groups of 2
+# slots), 3 assets (5 slots: one group of 4 and one slot; 12 slots: whole
+# groups only), FP32 and FP64.
+_PHILOX_STORE = {
+    "c3_short": CASES["c3_short"],
+    "c1": CASES["c1"],
+    "c2_philox": CASES["c2_philox"],
+    "c2d_philox": _small(CASES["c2d"], rng="philox"),
+    "c2_long_philox": _small(CASES["c2_long"], rng="philox"),
+    "c2_f64_philox": _small(CASES["c2_f64"], rng="philox"),
+}
+
+
+@pytest.mark.parametrize("name", list(_PHILOX_STORE))
+@pytest.mark.parametrize("n", [1000, 64])
+def test_path_store_without_recording_equals_recorded(name, n):
+    """Generating the path store alone (no words or normals recorded) takes
+    the Philox blocks in counter order; its prices equal, bit for bit, the
+    ones generated while recording, which test_streams_and_paths compares
+    with the oracle."""
+    import paper_2108_03076_amd as P
+    cfg = _PHILOX_STORE[name]
+    print(f"[parity] path store {name} n={n}", flush=True)
+    pay = gpu_payoff(cfg)
+    days, _ = pay.grid(cfg.tenv)
+    A = len(cfg.asset_labels)
+    dt = torch.float64 if cfg.precision == "f64" else torch.float32
+    rec = torch.empty(len(days) * A * n, dtype=dt, device="cuda")
+    words = torch.empty(len(days) * A * n, dtype=torch.int32, device="cuda")
+    normals = torch.empty(len(days) * A * n, dtype=dt, device="cuda")
+    P.gen_paths(pay, rec, words, normals, cfg.tenv, **model_kw(cfg), **opts_kw(cfg, n))
+    alone = torch.full_like(rec, float("nan"))
+    P.gen_paths(pay, alone, None, None, cfg.tenv, **model_kw(cfg), **opts_kw(cfg, n))
+    torch.cuda.synchronize()
+    assert torch.equal(alone, rec)
+    S = alone.double().cpu().numpy().reshape(len(days), A, n).transpose(2, 0, 1)
+    oS = oracle_problem(cfg).paths(np.arange(n))
+    tol = 1e-13 if cfg.precision == "f64" else 2e-5
+    assert np.max(np.abs(S / oS - 1)) < tol
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_payoffs_on_stored_paths(name):
     """Payoff arithmetic alone: the GPU evaluates its own stored paths, the
