@@ -61,8 +61,8 @@ OPS_IL_DOWN_AND_OUT = 4
 # copies of the same run (FETCH reads 0.5 KiB per KiB copied, WRITE 1.0;
 # profiles/pmc_jit_mc_batched_down_and_out_counters.md).  Valid only for the
 # engine sources it was measured on (hash below); otherwise reported as null.
-TRAFFIC = {"engine_sha256": "00c43e1950fb54bd5aa35be47b0851e244502b3202a3ef68252c1a49cf2d1cc6",
-           "fetch_kib": 18494.3, "write_kib": 6224.7, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC = {"engine_sha256": "2df20d5f431831c0387d04c1c070a19a125fcd6f54ab782bacffad2fcdf27fbb",
+           "fetch_kib": 17515.8, "write_kib": 6223.8, "fetch_scale": 2.0, "write_scale": 1.0}
 ENGINE_SOURCES = ("paper_2108_03076_amd/csrc/mc_engine.h", "paper_2108_03076_amd/csrc/pmc_device.h",
                   "paper_2108_03076_amd/csrc/codegen.cpp")
 C4_CPU_SAMPLE = (4, 1 << 12)   # oracle baseline: instances, paths each
