@@ -410,17 +410,18 @@ typedef struct pmc_train_opts {
   double lr_max, lr_min; /* cosine schedule from lr_max to lr_min over total_steps */
   int64_t total_steps;
   double beta1, beta2, eps;
-  int eager;          /* 0: each step is one replay of a captured graph; 1: the
-                         same kernels launched one by one (same results) */
+  int eager;          /* 0: steps replayed from a captured graph of 16 steps;
+                         1: the same kernels launched one by one (same results) */
 } pmc_train_opts;
 /* One pass over n samples (x_dev [n][n_in] float, raw inputs; y_dev [n]
  * float prices) in order, one Adam step per full batch (a trailing partial
  * batch is skipped); *mean_loss receives the mean squared error of the
  * scaled target over the pass.  o->batch must be a multiple of 64.  A step
- * (forward, loss and gradients, Adam with the BF16 repack of the weights)
- * is captured once as a HIP graph per batch size and replayed for every
- * step; the batch position, learning rate and bias corrections are read
- * from a device-side step record written at the start of the pass, so
+ * (forward, loss, gradients, Adam with the BF16 repack of the weights: 12
+ * launches) is captured 16 times in a row as one HIP graph per batch size,
+ * replayed for every 16 steps (the steps left over in a pass are launched
+ * one by one); the batch position, learning rate and bias corrections are
+ * read from a device-side step record written at the start of the pass, so
  * x_dev and y_dev may change between passes without a new capture.  The
  * call returns after the pass has finished on the device. */
 int pmc_mlp_train_epoch(pmc_mlp* m, const float* x_dev, const float* y_dev, int64_t n,

@@ -51,10 +51,13 @@ struct pmc_mlp {
   Buf W[4], Wt[4], Wf[4];
   // batch-sized work buffers
   int B = 0;
-  Buf X, Xt, Z[3], H[3], Ht[3], Y, dZ4, dZ4t, dZ[3], dZt[3], part_loss, loss_acc, partial;
+  // partial[2]: split-K weight-gradient partials, alternating between
+  // layers so that one layer's reduction runs beside the next one's products
+  Buf X, Xt, Z[3], H[3], Ht[3], Y, dZ4, dZ4t, dZ[3], dZt[3], part_loss, loss_acc, partial[2];
   Buf px, py;   // surrogate pricing: the in-box points and their predictions
   int64_t gen = 0;   // bumped whenever a work buffer moves (a captured step is then stale)
-  // one training step captured as a graph (batch size B_graph, buffers of generation gen_graph)
+  // kGraphSteps training steps captured as a graph (batch size B_graph,
+  // buffers of generation gen_graph)
   Buf tstep, hyper, part_epoch;   // the step record, per-step hyper-parameters, per-step loss partials
   std::vector<float> hyper_host;
   TrainStep tstep_host{};
@@ -114,7 +117,7 @@ int ensure_batch(pmc_mlp* M, int B) {
   MLP_TRY(M, M->dZ4t.ensure(b * 32 * 2));
   MLP_TRY(M, M->part_loss.ensure(((b + 255) / 256) * 8));
   MLP_TRY(M, M->loss_acc.ensure(8));
-  MLP_TRY(M, M->partial.ensure((size_t)kSplits * W * W * 4));
+  for (auto& p : M->partial) MLP_TRY(M, p.ensure((size_t)kSplits * W * W * 4));
   M->B = B;
   M->gen++;
   return PMC_OK;
@@ -157,25 +160,43 @@ int backward(pmc_mlp* M, const float* y, int n, int B, TrainStep* ts = nullptr) 
   MLP_TRY(M, mlp_loss(M->Y.as<float>(), y, n, B, (float)(1.0 / M->y_scale), 2.0f / (float)n,
                       M->dZ4.as<__bf16>(), M->dZ4t.as<__bf16>(),
                       ts ? M->part_epoch.as<double>() : M->part_loss.as<double>(), M->loss_acc.as<double>(), ts, s));
-  float* part = M->partial.as<float>();
-  // layer 4: dW4 = dZ4^T H3, db4, dZ3 = (dZ4 W4) * gelu'(Z3)
-  MLP_TRY(M, mlp_gemm_f32(32, W, B, M->dZ4t.as<__bf16>(), B, M->Ht[2].as<__bf16>(), B, kSplits, part, W, s));
-  MLP_TRY(M, mlp_layer_grads(part, kSplits, (size_t)32 * W, W, 1, W, g + M->oW[3], M->dZ4t.as<__bf16>(), B, 1,
-                             g + M->ob[3], nullptr, s));
-  MLP_TRY(M, mlp_gemm_back_hidden(B, W, 32, M->dZ4.as<__bf16>(), 32, M->Wt[3].as<__bf16>(), 32,
-                                  M->Z[2].as<float>(), M->dZ[2].as<__bf16>(), M->dZt[2].as<__bf16>(), s));
-  // layers 3 and 2
-  for (int l = 2; l >= 1; --l) {
-    MLP_TRY(M, mlp_gemm_f32(W, W, B, M->dZt[l].as<__bf16>(), B, M->Ht[l - 1].as<__bf16>(), B, kSplits, part, W, s));
-    MLP_TRY(M, mlp_layer_grads(part, kSplits, (size_t)W * W, W, W, W, g + M->oW[l], M->dZt[l].as<__bf16>(), B, W,
-                               g + M->ob[l], nullptr, s));
-    MLP_TRY(M, mlp_gemm_back_hidden(B, W, W, M->dZ[l].as<__bf16>(), W, M->Wt[l].as<__bf16>(), W,
-                                    M->Z[l - 1].as<float>(), M->dZ[l - 1].as<__bf16>(),
-                                    M->dZt[l - 1].as<__bf16>(), s));
-  }
-  // layer 1: dW1 = dZ1^T X (X^T has 32 padded rows), db1
-  MLP_TRY(M, mlp_gemm_f32(W, 32, B, M->dZt[0].as<__bf16>(), B, M->Xt.as<__bf16>(), B, kSplits, part, 32, s));
-  MLP_TRY(M, mlp_layer_grads(part, kSplits, (size_t)W * 32, 32, W, M->n_in, g + M->oW[0], M->dZt[0].as<__bf16>(), B,
+  // Five launches after the loss.  Each of the first four back-propagates
+  // to the layer below (`back`), forms the split-K weight-gradient partials
+  // of the layer whose dZ it reads (`wgrad`) and reduces the previous
+  // launch's partials with that layer's bias sums (`red`); the partials
+  // alternate between two buffers.  The last reduces layer 1's partials
+  // and advances the step record.
+  float* pa = M->partial[0].as<float>();
+  float* pb = M->partial[1].as<float>();
+  const MlpGemmJob none;
+  const MlpGradJob no_red;
+  // layer 4: dW4 partials (dZ4^T H3), dZ3 = (dZ4 W4) * gelu'(Z3)
+  MLP_TRY(M, mlp_backward_step(MlpGemmJob{B, W, 32, M->dZ4.as<__bf16>(), 32, M->Wt[3].as<__bf16>(), 32},
+                               M->Z[2].as<float>(), M->dZ[2].as<__bf16>(), M->dZt[2].as<__bf16>(),
+                               MlpGemmJob{32, W, B, M->dZ4t.as<__bf16>(), B, M->Ht[2].as<__bf16>(), B}, kSplits, pa,
+                               W, no_red, s));
+  // layer 3 and dZ2; dW4 and db4
+  MLP_TRY(M, mlp_backward_step(MlpGemmJob{B, W, W, M->dZ[2].as<__bf16>(), W, M->Wt[2].as<__bf16>(), W},
+                               M->Z[1].as<float>(), M->dZ[1].as<__bf16>(), M->dZt[1].as<__bf16>(),
+                               MlpGemmJob{W, W, B, M->dZt[2].as<__bf16>(), B, M->Ht[1].as<__bf16>(), B}, kSplits, pb,
+                               W, MlpGradJob{pa, (size_t)32 * W, W, 1, W, g + M->oW[3], M->dZ4t.as<__bf16>(), B, 1,
+                                             g + M->ob[3]},
+                               s));
+  // layer 2 and dZ1; dW3 and db3
+  MLP_TRY(M, mlp_backward_step(MlpGemmJob{B, W, W, M->dZ[1].as<__bf16>(), W, M->Wt[1].as<__bf16>(), W},
+                               M->Z[0].as<float>(), M->dZ[0].as<__bf16>(), M->dZt[0].as<__bf16>(),
+                               MlpGemmJob{W, W, B, M->dZt[1].as<__bf16>(), B, M->Ht[0].as<__bf16>(), B}, kSplits, pa,
+                               W, MlpGradJob{pb, (size_t)W * W, W, W, W, g + M->oW[2], M->dZt[2].as<__bf16>(), B, W,
+                                             g + M->ob[2]},
+                               s));
+  // layer 1 (X^T has 32 padded rows); dW2 and db2
+  MLP_TRY(M, mlp_backward_step(none, nullptr, nullptr, nullptr,
+                               MlpGemmJob{W, 32, B, M->dZt[0].as<__bf16>(), B, M->Xt.as<__bf16>(), B}, kSplits, pb,
+                               32, MlpGradJob{pa, (size_t)W * W, W, W, W, g + M->oW[1], M->dZt[1].as<__bf16>(), B, W,
+                                              g + M->ob[1]},
+                               s));
+  // dW1 and db1
+  MLP_TRY(M, mlp_layer_grads(pb, kSplits, (size_t)W * 32, 32, W, M->n_in, g + M->oW[0], M->dZt[0].as<__bf16>(), B,
                              W, g + M->ob[0], ts, s));
   return PMC_OK;
 }
@@ -364,11 +385,15 @@ int enqueue_step(pmc_mlp* M, const pmc_train_opts* o, int B, TrainStep* ts) {
   return PMC_OK;
 }
 
-// The training step captured as a graph for batch size B, the current work
-// buffers and the Adam constants (betas, eps); captured again when any of
-// them changes.  The batch position, the learning rate and the bias
-// corrections come from the step record, so one graph serves every step of
-// every epoch.  No memset is captured.
+// kGraphSteps training steps captured as one graph for batch size B, the
+// current work buffers and the Adam constants (betas, eps); captured again
+// when any of them changes.  The batch position, the learning rate and the
+// bias corrections come from the step record, so one graph serves every
+// run of kGraphSteps steps of every epoch (the steps left over are issued
+// one launch at a time).  No memset is captured.  (A graph of one step
+// cost about 5 us per replay more than its launches issued one by one;
+// with 16 steps per replay the two take the same time.)
+constexpr int kGraphSteps = 16;
 int step_graph(pmc_mlp* M, const pmc_train_opts* o, int B) {
   if (M->step_exec && M->B_graph == B && M->gen_graph == M->gen && M->adam_graph[0] == o->beta1 &&
       M->adam_graph[1] == o->beta2 && M->adam_graph[2] == o->eps)
@@ -382,7 +407,8 @@ int step_graph(pmc_mlp* M, const pmc_train_opts* o, int B) {
     return ctx_fail(M->ctx, PMC_E_HIP, std::string("training step capture: ") + hipGetErrorString(e));
   }
   M->capture = cap;
-  const int rc = enqueue_step(M, o, B, M->tstep.as<TrainStep>());
+  int rc = PMC_OK;
+  for (int k = 0; k < kGraphSteps && rc == PMC_OK; ++k) rc = enqueue_step(M, o, B, M->tstep.as<TrainStep>());
   M->capture = nullptr;
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(cap, &graph);
@@ -441,9 +467,15 @@ extern "C" int pmc_mlp_train_epoch(pmc_mlp* m, const float* x, const float* y, i
       if (rc != PMC_OK) return rc;
     }
   } else {
-    rc = step_graph(m, o, B);
-    if (rc != PMC_OK) return rc;
-    for (int64_t k = 0; k < steps; ++k) MLP_TRY(m, hipGraphLaunch(m->step_exec, s));
+    if (steps >= kGraphSteps) {
+      rc = step_graph(m, o, B);
+      if (rc != PMC_OK) return rc;
+    }
+    for (int64_t k = 0; k + kGraphSteps <= steps; k += kGraphSteps) MLP_TRY(m, hipGraphLaunch(m->step_exec, s));
+    for (int64_t k = steps / kGraphSteps * kGraphSteps; k < steps; ++k) {
+      rc = enqueue_step(m, o, B, m->tstep.as<TrainStep>());
+      if (rc != PMC_OK) return rc;
+    }
   }
   MLP_TRY(m, mlp_sum_parts(m->part_epoch.as<double>(), n_part, m->loss_acc.as<double>(), s));
   m->step += steps;

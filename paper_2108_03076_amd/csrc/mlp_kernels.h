@@ -26,9 +26,6 @@ struct MlpLayers {
   __bf16* Wf[4];   // fragment-ordered copies (fused inference)
 };
 
-// C [M x N] FP32 (split-K: `splits` partial products, C[z][M][ldc]) = A Bt^T.
-hipError_t mlp_gemm_f32(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb, int splits,
-                        float* C, int ldc, hipStream_t s);
 // Hidden layer forward with saved pre-activations Z, H = gelu(Z) and H^T.
 hipError_t mlp_gemm_hidden(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb,
                            const float* bias, float* Z, __bf16* H, __bf16* Ht, hipStream_t s);
@@ -38,9 +35,6 @@ hipError_t mlp_gemm_hidden_infer(int M, int N, int K, const __bf16* A, int lda, 
 // Output layer: y[row] = ((A Bt^T)[row][0] + bias[0]) * scale.
 hipError_t mlp_gemm_out(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb, const float* bias,
                         float* y, float scale, hipStream_t s);
-// Back-propagation through a hidden layer: dZ = (A Bt^T) * gelu'(Z), and dZ^T.
-hipError_t mlp_gemm_back_hidden(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb,
-                                const float* Z, __bf16* dZ, __bf16* dZt, hipStream_t s);
 // x raw inputs [n][n_in] (or, with ts, the step record's batch).
 hipError_t mlp_scale_inputs(const float* x, int n, int n_in, const float* lo, const float* hi, int B, __bf16* X,
                             __bf16* Xt, const TrainStep* ts, hipStream_t s);
@@ -58,6 +52,30 @@ hipError_t mlp_sum_parts(const double* part, int64_t n, double* acc, hipStream_t
 // launch; with ts_next, the launch also advances the step record.
 hipError_t mlp_layer_grads(const float* partial, int splits, size_t zstride, int ldp, int rows, int cols, float* g,
                            const __bf16* dZt, int B, int rows_b, float* gb, TrainStep* ts_next, hipStream_t s);
+// One launch of the backward pass that runs up to three independent jobs
+// side by side (a job with no rows is left out):
+//  * back: back-propagation to the layer below, dZ = (A Bt^T) * gelu'(Z)
+//    (BF16 [M][N]) and dZ^T ([N][M]), Z FP32 [M][N];
+//  * wgrad: a layer's weight gradient A Bt^T as `splits` partial products
+//    over chunks of K, into wpart [splits][M][ldc];
+//  * red: another layer's weight and bias gradients from its partials, as
+//    mlp_layer_grads (without a step record).
+// The jobs must not share outputs: red reads a partials buffer that wgrad
+// does not write; no job reads another job's output.
+struct MlpGemmJob {
+  int M = 0, N = 0, K = 0;
+  const __bf16* A = nullptr; int lda = 0;
+  const __bf16* Bt = nullptr; int ldb = 0;
+};
+struct MlpGradJob {
+  const float* partial = nullptr; size_t zstride = 0; int ldp = 0, rows = 0, cols = 0;
+  float* g = nullptr;
+  const __bf16* dZt = nullptr; int B = 0, rows_b = 0;
+  float* gb = nullptr;
+};
+hipError_t mlp_backward_step(const MlpGemmJob& back, const float* Z, __bf16* dZ, __bf16* dZt,
+                             const MlpGemmJob& wgrad, int splits, float* wpart, int ldc, const MlpGradJob& red,
+                             hipStream_t s);
 // Adam on the FP32 master parameters and the BF16 repack of the weights
 // (with ts: lr, c1, c2 from its current step).
 hipError_t mlp_adam_pack(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,

@@ -49,8 +49,9 @@ __device__ __forceinline__ float gelu_grad(float z) {
 }
 
 // C = A * Bt^T with A [M x K] and Bt [N x K] row-major BF16 (K contiguous).
-// Block: 4 waves on a 64 x 64 output tile, each wave one 32 x 32 MFMA tile;
-// blockIdx.z splits K into chunks of k_chunk.  M, N multiples of 32, K and
+// Block (bx, by, bz) of the grid (N/64, M/64, splits): 4 waves on a 64 x 64
+// output tile, each wave one 32 x 32 MFMA tile; bz selects the K chunk of
+// k_chunk.  M, N multiples of 32, K and
 // k_chunk multiples of 16, lda/ldb multiples of 8 (16-byte rows).
 // MFMA operand layout (32x32x16): lane l supplies row l%32 of A (and of Bt)
 // at k = 8*(l/32) .. +7; accumulator element e of lane l is
@@ -59,17 +60,19 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // (Epi::kTransposed) returns each element's transposed value; the wave
 // stages its 32 x 32 tile in LDS as [column][row] and writes each column's
 // 32 rows as one 64-byte segment (the scattered 2-byte stores of a direct
-// transposed write cost more than the products).
+// transposed write cost more than the products).  tt: the block's LDS
+// staging area (4 x 32 x kTld elements) for a transposed epilogue.  No
+// block-wide barrier: a wave outside the matrix returns at once.
+constexpr int kTld = 40;   // staged tile row: 32 rows + 8 padding
 template <class Epi>
-__global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const __bf16* __restrict__ A, int lda,
-                                                 const __bf16* __restrict__ Bt, int ldb, int k_chunk, Epi epi) {
-  constexpr int kTld = 40;   // staged tile row: 32 rows + 8 padding
-  __shared__ __bf16 tt[Epi::kTransposed ? 4 * 32 * kTld : 1];
+__device__ __forceinline__ void gemm_nt_block(int M, int N, int K, const __bf16* __restrict__ A, int lda,
+                                              const __bf16* __restrict__ Bt, int ldb, int k_chunk, const Epi& epi,
+                                              int bx, int by, int bz, __bf16* tt) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
-  const int n0 = blockIdx.x * 64 + (w & 1) * 32;
+  const int m0 = by * 64 + (w >> 1) * 32;
+  const int n0 = bx * 64 + (w & 1) * 32;
   if (m0 >= M || n0 >= N) return;
-  const int kbeg = blockIdx.z * k_chunk;
+  const int kbeg = bz * k_chunk;
   const int kend = min(K, kbeg + k_chunk);
   const int r = lane & 31, kh = (lane >> 5) * 8;
   const __bf16* pa = A + (size_t)(m0 + r) * lda + kh;
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const __bf
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int rl = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-      t[r * kTld + rl] = epi(m0 + rl, col, acc[e], (int)blockIdx.z);
+      t[r * kTld + rl] = epi(m0 + rl, col, acc[e], bz);
     }
     // the wave reads back what its lanes wrote (the fence orders the LDS
     // stores before the loads); lane l copies rows 16 (l%2) .. +15 of tile
@@ -115,9 +118,16 @@ __global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const __bf
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int row = m0 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-      epi(row, col, acc[e], (int)blockIdx.z);
+      epi(row, col, acc[e], bz);
     }
   }
+}
+
+template <class Epi>
+__global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const __bf16* __restrict__ A, int lda,
+                                                 const __bf16* __restrict__ Bt, int ldb, int k_chunk, Epi epi) {
+  __shared__ __bf16 tt[Epi::kTransposed ? 4 * 32 * kTld : 1];
+  gemm_nt_block(M, N, K, A, lda, Bt, ldb, k_chunk, epi, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, tt);
 }
 
 // Each epilogue also names the accumulators' starting value for an output
@@ -273,13 +283,12 @@ __global__ void k_sum_parts(const double* part, int n, double* out) {
 // record, block 0 also advances it: this launch is the last of a step's
 // gradients, and nothing in it reads the record.
 template <int SPLITS>
-__global__ __launch_bounds__(256) void k_layer_grads(const float* __restrict__ partial, size_t zstride, int ldp,
-                                                     int rows_real, int cols_real, float* __restrict__ g,
-                                                     const __bf16* __restrict__ dZt, int B, int rows_b,
-                                                     float* __restrict__ gb, int n_red, TrainStep* ts_next) {
-  if (ts_next && blockIdx.x == 0 && threadIdx.x == 0) ts_next->step += 1;
-  if ((int)blockIdx.x < n_red) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void layer_grads_block(const float* __restrict__ partial, size_t zstride, int ldp,
+                                                  int rows_real, int cols_real, float* __restrict__ g,
+                                                  const __bf16* __restrict__ dZt, int B, int rows_b,
+                                                  float* __restrict__ gb, int n_red, int bid) {
+  if (bid < n_red) {
+    const int i = bid * 256 + (int)threadIdx.x;
     if (i >= rows_real * cols_real) return;
     const int row = i / cols_real, col = i % cols_real;
     const float* p = partial + (size_t)row * ldp + col;
@@ -293,7 +302,7 @@ __global__ __launch_bounds__(256) void k_layer_grads(const float* __restrict__ p
     return;
   }
   const int lane = threadIdx.x & 63;
-  const int r = ((int)blockIdx.x - n_red) * 4 + (threadIdx.x >> 6);
+  const int r = (bid - n_red) * 4 + (threadIdx.x >> 6);
   if (r >= rows_b) return;
   const __bf16* p = dZt + (size_t)r * B;
   float sum = 0.0f;
@@ -305,6 +314,50 @@ __global__ __launch_bounds__(256) void k_layer_grads(const float* __restrict__ p
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
   if (lane == 0) gb[r] = sum;
+}
+template <int SPLITS>
+__global__ __launch_bounds__(256) void k_layer_grads(const float* __restrict__ partial, size_t zstride, int ldp,
+                                                     int rows_real, int cols_real, float* __restrict__ g,
+                                                     const __bf16* __restrict__ dZt, int B, int rows_b,
+                                                     float* __restrict__ gb, int n_red, TrainStep* ts_next) {
+  if (ts_next && blockIdx.x == 0 && threadIdx.x == 0) ts_next->step += 1;
+  layer_grads_block<SPLITS>(partial, zstride, ldp, rows_real, cols_real, g, dZt, B, rows_b, gb, n_red,
+                            (int)blockIdx.x);
+}
+
+// A backward launch's three jobs over one flat grid: blocks [0, nb) the
+// back-propagation GEMM, then nw blocks of the weight-gradient GEMM, then
+// the reduction's blocks (a count of 0 leaves a job out).  The jobs share
+// no outputs, and no block waits on another.
+struct GemmGrid {
+  int M, N, K; const __bf16* A; int lda; const __bf16* Bt; int ldb; int k_chunk; int gx, gy, gz;
+  __device__ int blocks() const { return gx * gy * gz; }
+};
+struct RedGrid {
+  const float* partial; size_t zstride; int ldp, rows, cols; float* g; const __bf16* dZt; int B, rows_b;
+  float* gb; int n_red, blocks;
+};
+__global__ __launch_bounds__(256) void k_backward_step(GemmGrid bj, EpiBackHidden be, GemmGrid wj, EpiF32 we,
+                                                       RedGrid rj) {
+  __shared__ __bf16 tt[4 * 32 * kTld];
+  int b = blockIdx.x;
+  const int nb = bj.blocks();
+  if (b < nb) {
+    gemm_nt_block(bj.M, bj.N, bj.K, bj.A, bj.lda, bj.Bt, bj.ldb, bj.k_chunk, be, b % bj.gx, (b / bj.gx) % bj.gy,
+                  b / (bj.gx * bj.gy), tt);
+    return;
+  }
+  b -= nb;
+  const int nw = wj.blocks();
+  if (b < nw) {
+    gemm_nt_block(wj.M, wj.N, wj.K, wj.A, wj.lda, wj.Bt, wj.ldb, wj.k_chunk, we, b % wj.gx, (b / wj.gx) % wj.gy,
+                  b / (wj.gx * wj.gy), tt);
+    return;
+  }
+  b -= nw;
+  if (b < rj.blocks)
+    layer_grads_block<16>(rj.partial, rj.zstride, rj.ldp, rj.rows, rj.cols, rj.g, rj.dZt, rj.B, rj.rows_b, rj.gb,
+                          rj.n_red, b);
 }
 
 // One Adam step on the FP32 master parameters followed by the BF16 copies
@@ -506,10 +559,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
 }  // namespace
 
-hipError_t mlp_gemm_f32(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb, int splits,
-                        float* C, int ldc, hipStream_t s) {
-  return gemm(M, N, K, A, lda, Bt, ldb, splits, EpiF32{C, ldc, (size_t)M * ldc}, s);
-}
 hipError_t mlp_gemm_hidden(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb,
                            const float* bias, float* Z, __bf16* H, __bf16* Ht, hipStream_t s) {
   return gemm(M, N, K, A, lda, Bt, ldb, 1, EpiHidden{bias, Z, N, H, N, Ht, M}, s);
@@ -521,10 +570,6 @@ hipError_t mlp_gemm_hidden_infer(int M, int N, int K, const __bf16* A, int lda, 
 hipError_t mlp_gemm_out(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb, const float* bias,
                         float* y, float scale, hipStream_t s) {
   return gemm(M, N, K, A, lda, Bt, ldb, 1, EpiOut{bias, y, scale}, s);
-}
-hipError_t mlp_gemm_back_hidden(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb,
-                                const float* Z, __bf16* dZ, __bf16* dZt, hipStream_t s) {
-  return gemm(M, N, K, A, lda, Bt, ldb, 1, EpiBackHidden{Z, N, dZ, N, dZt, M}, s);
 }
 hipError_t mlp_scale_inputs(const float* x, int n, int n_in, const float* lo, const float* hi, int B, __bf16* X,
                             __bf16* Xt, const TrainStep* ts, hipStream_t s) {
@@ -550,6 +595,46 @@ hipError_t mlp_layer_grads(const float* partial, int splits, size_t zstride, int
   const int n_red = (rows * cols + 255) / 256;
   hipLaunchKernelGGL(k_layer_grads<16>, dim3(n_red + (rows_b + 3) / 4), dim3(256), 0, s, partial, zstride, ldp, rows,
                      cols, g, dZt, B, rows_b, gb, n_red, ts_next);
+  return hipGetLastError();
+}
+namespace {
+// The grid of one GEMM job (validated as gemm() does); a job with M = 0
+// gets no blocks.
+bool gemm_grid(const MlpGemmJob& j, int splits, GemmGrid& g) {
+  g = GemmGrid{j.M, j.N, j.K, j.A, j.lda, j.Bt, j.ldb, 0, 0, 0, 0};
+  if (j.M == 0) return true;
+  if (j.M < 0 || j.N < 1 || j.K < 16 || j.M % 32 || j.N % 32 || j.K % 16 || j.lda % 8 || j.ldb % 8 || splits < 1 ||
+      !j.A || !j.Bt)
+    return false;
+  int chunk = (j.K + splits - 1) / splits;
+  chunk = (chunk + 15) / 16 * 16;
+  g.k_chunk = chunk;
+  g.gx = (j.N + 63) / 64;
+  g.gy = (j.M + 63) / 64;
+  g.gz = splits;
+  return true;
+}
+}  // namespace
+
+hipError_t mlp_backward_step(const MlpGemmJob& back, const float* Z, __bf16* dZ, __bf16* dZt,
+                             const MlpGemmJob& wgrad, int splits, float* wpart, int ldc, const MlpGradJob& red,
+                             hipStream_t s) {
+  GemmGrid bj, wj;
+  if (!gemm_grid(back, 1, bj) || !gemm_grid(wgrad, splits, wj)) return hipErrorInvalidValue;
+  if (back.M && (!Z || !dZ || !dZt)) return hipErrorInvalidValue;
+  if (wgrad.M && (!wpart || ldc < wgrad.N)) return hipErrorInvalidValue;
+  RedGrid rj{red.partial, red.zstride, red.ldp, red.rows, red.cols, red.g, red.dZt, red.B, red.rows_b, red.gb, 0, 0};
+  if (red.rows) {
+    if (red.rows < 1 || red.cols < 1 || red.rows_b < 1 || red.B % 8 || !red.partial || !red.g || !red.dZt || !red.gb)
+      return hipErrorInvalidValue;
+    rj.n_red = (red.rows * red.cols + 255) / 256;
+    rj.blocks = rj.n_red + (red.rows_b + 3) / 4;
+  }
+  const int64_t total = (int64_t)bj.gx * bj.gy * bj.gz + (int64_t)wj.gx * wj.gy * wj.gz + rj.blocks;
+  if (total < 1 || total > INT32_MAX) return hipErrorInvalidValue;
+  const EpiBackHidden be{Z, back.N, dZ, back.N, dZt, back.M};
+  const EpiF32 we{wpart, ldc, (size_t)wgrad.M * ldc};
+  hipLaunchKernelGGL(k_backward_step, dim3((unsigned)total), dim3(256), 0, s, bj, be, wj, we, rj);
   return hipGetLastError();
 }
 hipError_t mlp_adam_pack(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,

@@ -183,18 +183,21 @@ def test_adam_steps_and_cosine_schedule_match_oracle():
 
 
 def test_graph_training_steps_equal_eager_launches():
-    """Training steps replayed from the captured graph give the same master
-    weights, BF16 copies (through inference) and losses, bit for bit, as
-    the same kernels launched one by one: over several passes whose input
-    tensors move between passes, with other device work and
-    synchronisations between the replays, and across a change of batch size
-    (a new capture)."""
+    """Training steps replayed from the captured graph (16 steps per replay,
+    the rest of a pass launched one by one) give the same master weights,
+    BF16 copies (through inference) and losses, bit for bit, as the same
+    kernels launched one by one: over several passes whose input tensors
+    move between passes, with other device work and synchronisations
+    between the replays, and across changes of batch size (a new capture;
+    18 steps: one replay and two single steps; 36: two replays and four;
+    9: no replay)."""
     g_net, e_net = _net(seed=13), _net(seed=13)
-    x, y = _data(4096, 14)
+    n = 9216
+    x, y = _data(n, 14)
     xq = torch.tensor(_data(512, 15)[0], dtype=torch.float32, device="cuda")
-    total = 40
-    for epoch, batch in enumerate((512, 512, 512, 1024, 512)):
-        perm = np.random.default_rng(epoch).permutation(4096)
+    total = 120
+    for epoch, batch in enumerate((512, 512, 256, 1024, 512)):
+        perm = np.random.default_rng(epoch).permutation(n)
         xt = torch.tensor(x[perm], dtype=torch.float32, device="cuda")
         yt = torch.tensor(y[perm], dtype=torch.float32, device="cuda")
         lg = g_net.train_epoch(xt, yt, batch=batch, lr_max=2e-3, lr_min=1e-5, total_steps=total)
