@@ -51,59 +51,99 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // C = A * Bt^T with A [M x K] and Bt [N x K] row-major BF16 (K contiguous).
 // Block (bx, by, bz) of the grid (N/64, M/64, splits): 4 waves on a 64 x 64
 // output tile, each wave one 32 x 32 MFMA tile; bz selects the K chunk of
-// k_chunk.  M, N multiples of 32, K and
-// k_chunk multiples of 16, lda/ldb multiples of 8 (16-byte rows).
+// k_chunk.  M, N multiples of 32, K and k_chunk multiples of 16, lda/ldb
+// multiples of 8 (16-byte rows).
 // MFMA operand layout (32x32x16): lane l supplies row l%32 of A (and of Bt)
 // at k = 8*(l/32) .. +7; accumulator element e of lane l is
-// C[8*(e/4) + 4*(l/32) + e%4][l%32].  The k loop issues four steps' loads
-// before their products.  An epilogue with a transposed BF16 output
-// (Epi::kTransposed) returns each element's transposed value; the wave
-// stages its 32 x 32 tile in LDS as [column][row] and writes each column's
-// 32 rows as one 64-byte segment (the scattered 2-byte stores of a direct
-// transposed write cost more than the products).  tt: the block's LDS
-// staging area (4 x 32 x kTld elements) for a transposed epilogue.  No
-// block-wide barrier: a wave outside the matrix returns at once.
-constexpr int kTld = 40;   // staged tile row: 32 rows + 8 padding
+// C[8*(e/4) + 4*(l/32) + e%4][l%32].
+// The block stages its 64 rows of A and of Bt through LDS, 64 k at a time
+// in two alternating buffers: a thread loads two 16-byte pieces of each
+// (rows t/8 and t/8 + 32, k offset 8 (t%8)), so one wave load reads eight
+// whole rows of 128 bytes; read directly, each lane's own row made every
+// load touch 32 cache lines, and the vector-memory pipeline bound the
+// kernel.  The loads of four stages are issued together.  The products run in the same k order as before.  An epilogue
+// with a transposed BF16 output (Epi::kTransposed) returns each element's
+// transposed value; the wave stages its 32 x 32 tile in LDS as
+// [column][row] and writes each column's 32 rows as one 64-byte segment.
+// lds: kGemmLds elements.  Every wave of the block takes part in the loads
+// and barriers; a wave outside the matrix skips the products.
+constexpr int kTld = 40;              // staged output tile row: 32 rows + 8 padding
+constexpr int kSld = 72;              // staged operand row: 64 k + 8 padding
+constexpr int kStage = 64 * kSld;     // one operand's stage
+constexpr int kGemmLds = 4 * kStage;  // A and Bt, two stages each: 36,864 bytes
 template <class Epi>
 __device__ __forceinline__ void gemm_nt_block(int M, int N, int K, const __bf16* __restrict__ A, int lda,
                                               const __bf16* __restrict__ Bt, int ldb, int k_chunk, const Epi& epi,
-                                              int bx, int by, int bz, __bf16* tt) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = by * 64 + (w >> 1) * 32;
-  const int n0 = bx * 64 + (w & 1) * 32;
-  if (m0 >= M || n0 >= N) return;
+                                              int bx, int by, int bz, __bf16* lds) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int mb = by * 64, nb = bx * 64;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int m0 = mb + wm, n0 = nb + wn;
+  const bool active = m0 < M && n0 < N;
   const int kbeg = bz * k_chunk;
   const int kend = min(K, kbeg + k_chunk);
   const int r = lane & 31, kh = (lane >> 5) * 8;
-  const __bf16* pa = A + (size_t)(m0 + r) * lda + kh;
-  const __bf16* pb = Bt + (size_t)(n0 + r) * ldb + kh;
+  // this thread's pieces of a stage
+  const int lr = t >> 3, lk = (t & 7) * 8;
+  const bool a0 = mb + lr < M, a1 = mb + lr + 32 < M, b0 = nb + lr < N, b1 = nb + lr + 32 < N;
+  const __bf16* ga = A + (size_t)(mb + lr) * lda + lk;
+  const __bf16* gb = Bt + (size_t)(nb + lr) * ldb + lk;
+  // up to four stages (256 k) in flight at once: one memory latency per
+  // 256 k rather than one per stage
+  bf16x8 ra[4][2], rb[4][2];
   f32x16 acc;
-  const float a0 = epi.init(n0 + r);
+  const float c0 = active ? epi.init(n0 + r) : 0.0f;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) acc[e] = a0;
-  int k = kbeg;
-  for (; k + 64 <= kend; k += 64) {
-    bf16x8 a[4], b[4];
+  for (int e = 0; e < 16; ++e) acc[e] = c0;
+  for (int k0 = kbeg; k0 < kend; k0 += 256) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = *reinterpret_cast<const bf16x8*>(pa + k + 16 * u);
-      b[u] = *reinterpret_cast<const bf16x8*>(pb + k + 16 * u);
+    for (int q = 0; q < 4; ++q) {
+      bf16x8 z;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) z[j] = to_bf16(0.0f);
+      const int k = k0 + 64 * q;
+      const bool in = k + lk < kend;
+      ra[q][0] = (in && a0) ? *reinterpret_cast<const bf16x8*>(ga + k) : z;
+      ra[q][1] = (in && a1) ? *reinterpret_cast<const bf16x8*>(ga + (size_t)32 * lda + k) : z;
+      rb[q][0] = (in && b0) ? *reinterpret_cast<const bf16x8*>(gb + k) : z;
+      rb[q][1] = (in && b1) ? *reinterpret_cast<const bf16x8*>(gb + (size_t)32 * ldb + k) : z;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u], b[u], acc, 0, 0, 0);
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + 64 * q;
+      if (k >= kend) break;
+      // stage q goes to buffer q % 2, last read two stages ago (before the
+      // previous stage's barrier)
+      __bf16* as = lds + (q & 1) * 2 * kStage;
+      __bf16* bs = as + kStage;
+      *reinterpret_cast<bf16x8*>(as + lr * kSld + lk) = ra[q][0];
+      *reinterpret_cast<bf16x8*>(as + (lr + 32) * kSld + lk) = ra[q][1];
+      *reinterpret_cast<bf16x8*>(bs + lr * kSld + lk) = rb[q][0];
+      *reinterpret_cast<bf16x8*>(bs + (lr + 32) * kSld + lk) = rb[q][1];
+      __syncthreads();
+      if (active) {
+        const __bf16* pa = as + (wm + r) * kSld + kh;
+        const __bf16* pb = bs + (wn + r) * kSld + kh;
+        const int steps = min(4, (kend - k) / 16);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (u < steps)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8*>(pa + 16 * u),
+                                                          *reinterpret_cast<const bf16x8*>(pb + 16 * u), acc, 0,
+                                                          0, 0);
+      }
+    }
   }
-  for (; k < kend; k += 16) {
-    const bf16x8 a = *reinterpret_cast<const bf16x8*>(pa + k);
-    const bf16x8 b = *reinterpret_cast<const bf16x8*>(pb + k);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-  }
+  // every wave's products are done before the staging area is reused
+  __syncthreads();
+  if (!active) return;
   const int col = n0 + r;
   if constexpr (Epi::kTransposed) {
-    __bf16* t = tt + w * 32 * kTld;
+    __bf16* tt = lds + w * 32 * kTld;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int rl = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-      t[r * kTld + rl] = epi(m0 + rl, col, acc[e], bz);
+      tt[r * kTld + rl] = epi(m0 + rl, col, acc[e], bz);
     }
     // the wave reads back what its lanes wrote (the fence orders the LDS
     // stores before the loads); lane l copies rows 16 (l%2) .. +15 of tile
@@ -111,8 +151,8 @@ __device__ __forceinline__ void gemm_nt_block(int M, int N, int K, const __bf16*
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const int c = lane >> 1, h = (lane & 1) * 16;
-    const bf16x8 v0 = *reinterpret_cast<const bf16x8*>(t + c * kTld + h);
-    const bf16x8 v1 = *reinterpret_cast<const bf16x8*>(t + c * kTld + h + 8);
+    const bf16x8 v0 = *reinterpret_cast<const bf16x8*>(tt + c * kTld + h);
+    const bf16x8 v1 = *reinterpret_cast<const bf16x8*>(tt + c * kTld + h + 8);
     epi.store_t(n0 + c, m0 + h, v0, v1);
   } else {
 #pragma unroll
@@ -126,8 +166,8 @@ __device__ __forceinline__ void gemm_nt_block(int M, int N, int K, const __bf16*
 template <class Epi>
 __global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const __bf16* __restrict__ A, int lda,
                                                  const __bf16* __restrict__ Bt, int ldb, int k_chunk, Epi epi) {
-  __shared__ __bf16 tt[Epi::kTransposed ? 4 * 32 * kTld : 1];
-  gemm_nt_block(M, N, K, A, lda, Bt, ldb, k_chunk, epi, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, tt);
+  __shared__ __bf16 lds[kGemmLds];
+  gemm_nt_block(M, N, K, A, lda, Bt, ldb, k_chunk, epi, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, lds);
 }
 
 // Each epilogue also names the accumulators' starting value for an output
@@ -328,7 +368,8 @@ __global__ __launch_bounds__(256) void k_layer_grads(const float* __restrict__ p
 // A backward launch's three jobs over one flat grid: blocks [0, nb) the
 // back-propagation GEMM, then nw blocks of the weight-gradient GEMM, then
 // the reduction's blocks (a count of 0 leaves a job out).  The jobs share
-// no outputs, and no block waits on another.
+// no outputs, and no block waits on another (a block's barriers are its
+// own, every thread of it on the same job).
 struct GemmGrid {
   int M, N, K; const __bf16* A; int lda; const __bf16* Bt; int ldb; int k_chunk; int gx, gy, gz;
   __device__ int blocks() const { return gx * gy * gz; }
@@ -339,19 +380,19 @@ struct RedGrid {
 };
 __global__ __launch_bounds__(256) void k_backward_step(GemmGrid bj, EpiBackHidden be, GemmGrid wj, EpiF32 we,
                                                        RedGrid rj) {
-  __shared__ __bf16 tt[4 * 32 * kTld];
+  __shared__ __bf16 lds[kGemmLds];
   int b = blockIdx.x;
   const int nb = bj.blocks();
   if (b < nb) {
     gemm_nt_block(bj.M, bj.N, bj.K, bj.A, bj.lda, bj.Bt, bj.ldb, bj.k_chunk, be, b % bj.gx, (b / bj.gx) % bj.gy,
-                  b / (bj.gx * bj.gy), tt);
+                  b / (bj.gx * bj.gy), lds);
     return;
   }
   b -= nb;
   const int nw = wj.blocks();
   if (b < nw) {
     gemm_nt_block(wj.M, wj.N, wj.K, wj.A, wj.lda, wj.Bt, wj.ldb, wj.k_chunk, we, b % wj.gx, (b / wj.gx) % wj.gy,
-                  b / (wj.gx * wj.gy), tt);
+                  b / (wj.gx * wj.gy), lds);
     return;
   }
   b -= nw;
