@@ -90,9 +90,11 @@ def train(sur: Surrogate, x, y, *, epochs, batch=4096, lr_max=1e-3, lr_min=1e-5,
     n = int(y.numel())
     steps = max(1, n // batch) * epochs
     losses = []
-    g = torch.Generator(device="cpu").manual_seed(0)
+    # the shuffle runs on the device (on torch's current stream, which a
+    # context uses unless given another)
+    g = torch.Generator(device=x.device).manual_seed(0)
     for e in range(epochs):
-        perm = torch.randperm(n, generator=g).to(x.device)
+        perm = torch.randperm(n, generator=g, device=x.device)
         xe, ye = x[perm].contiguous(), y[perm].contiguous()
         losses.append(sur.train_epoch(xe, ye, batch=batch, lr_max=lr_max, lr_min=lr_min, total_steps=steps))
         if log:
