@@ -453,21 +453,24 @@ __global__ void k_pack(const float* __restrict__ master, int out, int in, int ou
 // Fused inference for width 256: a block carries 64 samples through the
 // four layers with their BF16 activations in LDS, in two buffers (a layer
 // reads one and writes the other, so one barrier per layer suffices; rows
-// padded by 8 elements): 67.6 KB, so two blocks share a CU and each SIMD
-// runs two waves, one's matrix products overlapping the other's GELU.  The
-// matrix cores compute C^T = W X^T: operand A is a weight fragment (rows =
-// output features), operand B an activation fragment (rows = samples), so
-// a lane's accumulator holds four consecutive features of one sample
-// (elements 4q .. 4q + 3 are features 8q + 4 (lane / 32) + 0..3 of the
-// tile, sample lane % 32), which GELU turns into one 8-byte LDS store.
-// The accumulators start at the bias, as in the per-layer kernels, whose
-// outputs these are bit for bit.  Wave w owns features 64w .. 64w + 63 of
-// every layer and holds their weights in registers for both 32-sample
-// tiles; the GELU of the first tile has the products of the second to
-// overlap with.
+// padded by 8 elements): 67.6 KB, so two blocks share a CU.  The matrix
+// cores compute C^T = W X^T: operand A is a weight fragment (rows = output
+// features), operand B an activation fragment (rows = samples), so a lane's
+// accumulator holds four consecutive features of one sample (elements
+// 4q .. 4q + 3 are features 8q + 4 (lane / 32) + 0..3 of the tile, sample
+// lane % 32), which GELU turns into one 8-byte LDS store.  The accumulators
+// start at the bias, as in the per-layer kernels, whose outputs these are
+// bit for bit.  A block has eight waves; wave w owns features 32w .. 32w + 31
+// (one feature tile) of every layer and holds their weights in registers
+// (64 of its 124 vector registers) for both 32-sample tiles, so four waves
+// share each SIMD and one's matrix products overlap another's GELU; within
+// a wave, the GELU of the first sample tile is interleaved with the
+// products of the second.  (Four waves per block, each holding two feature
+// tiles' weights in 242 registers, ran two waves per SIMD: 3-4 % slower.)
 constexpr int kInferRows = 64;
 constexpr int kInferW = 256;
 constexpr int kInferLd = kInferW + 8;
+constexpr int kInferThreads = 512;
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void bias_init(f32x16& acc, const float* __restrict__ b) {
@@ -480,18 +483,15 @@ __device__ __forceinline__ void bias_init(f32x16& acc, const float* __restrict__
 }
 
 // This wave's weight fragments of a layer with K = 16 KS inputs, k steps
-// K0 .. K1 - 1, from the fragment-ordered copy Wf: output tiles 2w + ft
-// (features 64w + 32 ft ..), one 1 KB wave load each.
-// With OUT set, the layer is the output layer (one 32-row tile, shared by
-// all waves) and only feature tile 0 is loaded.
+// K0 .. K1 - 1, from the fragment-ordered copy Wf: output tile w (features
+// 32w ..), one 1 KB wave load per k step.  With OUT set, the layer is the
+// output layer (one 32-row tile, loaded by every wave).
 template <int KS, int K0 = 0, int K1 = KS, bool OUT = false>
-__device__ __forceinline__ void load_weights(bf16x8 (&wf)[16][2], const __bf16* __restrict__ Wf) {
+__device__ __forceinline__ void load_weights(bf16x8 (&wf)[16], const __bf16* __restrict__ Wf) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int k = K0; k < K1; ++k)
-#pragma unroll
-    for (int ft = 0; ft < (OUT ? 1 : 2); ++ft)
-      wf[k][ft] = *reinterpret_cast<const bf16x8*>(Wf + ((size_t)((OUT ? 0 : 2 * w + ft) * KS + k) * 64 + lane) * 8);
+    wf[k] = *reinterpret_cast<const bf16x8*>(Wf + ((size_t)((OUT ? 0 : w) * KS + k) * 64 + lane) * 8);
 }
 
 // GELU of accumulator elements 4q .. 4q + 3 of one tile into the lane's
@@ -507,52 +507,43 @@ __device__ __forceinline__ void gelu_quad(const f32x16& acc, int q, __bf16* dst)
 
 // One hidden layer (K = 16 KS inputs, 256 outputs) for the block's 64
 // samples: out = gelu(b + W in).  The products of sample tile 1 are
-// written interleaved with the GELU of tile 0 (one quad of one feature
-// tile per k step), so the matrix cores and the vector unit of a wave
-// work at the same time; the next layer's weights are loaded into the
-// weight registers once this layer's products are issued, half before
-// and half after the GELU of tile 1.
+// written interleaved with the GELU of tile 0 (one quad per four k steps),
+// so the matrix cores and the vector unit of a wave work at the same time;
+// the next layer's weights are loaded into the weight registers once this
+// layer's products are issued, half before and half after the GELU of
+// tile 1 (their latency hides behind the GELU and the barrier).
 template <int KS, int KSN, bool NEXT_OUT = false>
-__device__ __forceinline__ void hidden_layer(const __bf16* in, __bf16* out, bf16x8 (&wf)[16][2],
+__device__ __forceinline__ void hidden_layer(const __bf16* in, __bf16* out, bf16x8 (&wf)[16],
                                              const float* __restrict__ bl, const __bf16* __restrict__ Wnext) {
   const int lane = threadIdx.x & 63, r = lane & 31, kh = (lane >> 5) * 8, w = threadIdx.x >> 6;
   const int h4 = 4 * (lane >> 5);
-  f32x16 acc[2][2];   // [sample tile][feature tile]
+  f32x16 acc[2];   // [sample tile]
 #pragma unroll
-  for (int st = 0; st < 2; ++st)
-#pragma unroll
-    for (int ft = 0; ft < 2; ++ft) bias_init(acc[st][ft], bl + 64 * w + 32 * ft);
+  for (int st = 0; st < 2; ++st) bias_init(acc[st], bl + 32 * w);
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
     const bf16x8 b = *reinterpret_cast<const bf16x8*>(in + r * kInferLd + 16 * k + kh);
-#pragma unroll
-    for (int ft = 0; ft < 2; ++ft)
-      acc[0][ft] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[k][ft], b, acc[0][ft], 0, 0, 0);
+    acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[k], b, acc[0], 0, 0, 0);
   }
-  __bf16* o0 = out + r * kInferLd + 64 * w + h4;
+  __bf16* o0 = out + r * kInferLd + 32 * w + h4;
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
     const bf16x8 b = *reinterpret_cast<const bf16x8*>(in + (32 + r) * kInferLd + 16 * k + kh);
-#pragma unroll
-    for (int ft = 0; ft < 2; ++ft)
-      acc[1][ft] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[k][ft], b, acc[1][ft], 0, 0, 0);
-    if (KS == 16 && k < 8) gelu_quad(acc[0][k >> 2], k & 3, o0 + 32 * (k >> 2));
+    acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[k], b, acc[1], 0, 0, 0);
+    if (KS == 16 && (k & 3) == 0) gelu_quad(acc[0], k >> 2, o0);
   }
   if (KS != 16) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) gelu_quad(acc[0][i >> 2], i & 3, o0 + 32 * (i >> 2));
+    for (int q = 0; q < 4; ++q) gelu_quad(acc[0], q, o0);
   }
   load_weights<KSN, 0, KSN / 2, NEXT_OUT>(wf, Wnext);
-  __bf16* o1 = out + (32 + r) * kInferLd + 64 * w + h4;
+  __bf16* o1 = out + (32 + r) * kInferLd + 32 * w + h4;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) gelu_quad(acc[1][i >> 2], i & 3, o1 + 32 * (i >> 2));
+  for (int q = 0; q < 4; ++q) gelu_quad(acc[1], q, o1);
   load_weights<KSN, KSN / 2, KSN, NEXT_OUT>(wf, Wnext);
 }
 
-// A layer's weight loads are issued around the previous layer's GELU (the
-// weight registers are free once its products are issued), so their
-// latency is hidden behind the GELU and the barrier.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_infer256(
+__global__ __launch_bounds__(kInferThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_mlp_infer256(
     const float* __restrict__ x, int n, int n_in, const float* __restrict__ lohi, const __bf16* __restrict__ W1,
     const float* __restrict__ b1, const __bf16* __restrict__ W2, const float* __restrict__ b2,
     const __bf16* __restrict__ W3, const float* __restrict__ b3, const __bf16* __restrict__ W4,
@@ -560,9 +551,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   __shared__ __bf16 act[2][kInferRows * kInferLd];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 31, kh = (lane >> 5) * 8;
   const int64_t g0 = (int64_t)blockIdx.x * kInferRows;   // global row of the block's first row
-  bf16x8 wf[16][2];
+  bf16x8 wf[16];
   load_weights<1>(wf, W1);
-  {   // scaled inputs in columns 0..15 (zero beyond n_in and beyond n): thread t fills row t/4, columns 4 (t%4) ..
+  if (threadIdx.x < 4 * kInferRows) {
+    // scaled inputs in columns 0..15 (zero beyond n_in and beyond n):
+    // thread t fills row t/4, columns 4 (t%4) ..
     const int row = threadIdx.x >> 2, j0 = 4 * (threadIdx.x & 3);
     const int64_t gi = g0 + row;
     bf16x4 v;
@@ -581,7 +574,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   hidden_layer<16, 16>(act[1], act[0], wf, b2, W3);
   __syncthreads();
   // the output layer's fragments (W4: one 32-row tile, 16 k steps) are
-  // loaded as feature tile 0 of every wave
+  // loaded by every wave
   hidden_layer<16, 16, true>(act[0], act[1], wf, b3, W4);
   __syncthreads();
   if (w < 2) {   // waves 0 and 1: samples 32w .. 32w + 31; feature 0 is element 0 of lanes 0..31
@@ -592,7 +585,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const bf16x8 b = *reinterpret_cast<const bf16x8*>(&act[1][(32 * w + r) * kInferLd + 16 * k + kh]);
-      out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[k][0], b, out, 0, 0, 0);
+      out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[k], b, out, 0, 0, 0);
     }
     if (lane < 32 && g0 + 32 * w + r < n) y[g0 + 32 * w + r] = out[0] * y_scale;
   }
@@ -688,8 +681,8 @@ hipError_t mlp_infer256(const float* x, int n, int n_in, const float* lohi, cons
                         const __bf16* W2, const float* b2, const __bf16* W3, const float* b3, const __bf16* W4,
                         const float* b4, float y_scale, float* y, hipStream_t s) {
   if (n < 1 || n_in < 1 || n_in > 16) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_mlp_infer256, dim3((n + kInferRows - 1) / kInferRows), dim3(256), 0, s, x, n, n_in, lohi, W1,
-                     b1, W2, b2, W3, b3, W4, b4, y_scale, y);
+  hipLaunchKernelGGL(k_mlp_infer256, dim3((n + kInferRows - 1) / kInferRows), dim3(kInferThreads), 0, s, x, n, n_in,
+                     lohi, W1, b1, W2, b2, W3, b3, W4, b4, y_scale, y);
   return hipGetLastError();
 }
 hipError_t mlp_pack(const float* master, int out, int in, int out_pad, int in_pad, __bf16* W, __bf16* Wt,
