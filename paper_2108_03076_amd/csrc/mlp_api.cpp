@@ -160,12 +160,14 @@ int backward(pmc_mlp* M, const float* y, int n, int B, TrainStep* ts = nullptr) 
   MLP_TRY(M, mlp_loss(M->Y.as<float>(), y, n, B, (float)(1.0 / M->y_scale), 2.0f / (float)n,
                       M->dZ4.as<__bf16>(), M->dZ4t.as<__bf16>(),
                       ts ? M->part_epoch.as<double>() : M->part_loss.as<double>(), M->loss_acc.as<double>(), ts, s));
-  // Five launches after the loss.  Each of the first four back-propagates
-  // to the layer below (`back`), forms the split-K weight-gradient partials
-  // of the layer whose dZ it reads (`wgrad`) and reduces the previous
-  // launch's partials with that layer's bias sums (`red`); the partials
-  // alternate between two buffers.  The last reduces layer 1's partials
-  // and advances the step record.
+  // Four launches after the loss.  Each back-propagates to the layer below
+  // (`back`, but the last), forms the split-K weight-gradient partials of
+  // the layer whose dZ it reads (`wgrad`) and reduces the previous launch's
+  // partials with that layer's bias sums (`red`, but the first); the
+  // partials alternate between two buffers.  The last also sums layer 1's
+  // bias gradient and advances the step record; layer 1's weight partials
+  // are summed by Adam in a training step (in the same order), and by one
+  // more launch otherwise.
   float* pa = M->partial[0].as<float>();
   float* pb = M->partial[1].as<float>();
   const MlpGemmJob none;
@@ -189,15 +191,20 @@ int backward(pmc_mlp* M, const float* y, int n, int B, TrainStep* ts = nullptr) 
                                W, MlpGradJob{pb, (size_t)W * W, W, W, W, g + M->oW[2], M->dZt[2].as<__bf16>(), B, W,
                                              g + M->ob[2]},
                                s));
-  // layer 1 (X^T has 32 padded rows); dW2 and db2
+  // layer 1 (X^T has 32 padded rows); dW2 and db2; db1; the step record
+  // advances (the loss has read it)
+  MlpGradJob red2{pa, (size_t)W * W, W, W, W, g + M->oW[1], M->dZt[1].as<__bf16>(), B, W, g + M->ob[1]};
+  red2.dZt2 = M->dZt[0].as<__bf16>();
+  red2.rows_b2 = W;
+  red2.gb2 = g + M->ob[0];
+  red2.ts_next = ts;
   MLP_TRY(M, mlp_backward_step(none, nullptr, nullptr, nullptr,
                                MlpGemmJob{W, 32, B, M->dZt[0].as<__bf16>(), B, M->Xt.as<__bf16>(), B}, kSplits, pb,
-                               32, MlpGradJob{pa, (size_t)W * W, W, W, W, g + M->oW[1], M->dZt[1].as<__bf16>(), B, W,
-                                              g + M->ob[1]},
-                               s));
-  // dW1 and db1
-  MLP_TRY(M, mlp_layer_grads(pb, kSplits, (size_t)W * 32, 32, W, M->n_in, g + M->oW[0], M->dZt[0].as<__bf16>(), B,
-                             W, g + M->ob[0], ts, s));
+                               32, red2, s));
+  // dW1: in a training step, Adam sums its partials itself; otherwise here
+  if (!ts)
+    MLP_TRY(M, mlp_layer_grads(pb, kSplits, (size_t)W * 32, 32, W, M->n_in, g + M->oW[0], nullptr, B, 0, nullptr,
+                               nullptr, s));
   return PMC_OK;
 }
 
@@ -381,7 +388,7 @@ int enqueue_step(pmc_mlp* M, const pmc_train_opts* o, int B, TrainStep* ts) {
   hipStream_t s = stream_of(M);
   MLP_TRY(M, mlp_adam_pack(M->master.as<float>(), M->m.as<float>(), M->v.as<float>(), M->grad.as<float>(),
                            M->n_params, 0.0f, (float)o->beta1, (float)o->beta2, (float)o->eps, 1.0f, 1.0f,
-                           M->layers(), ts, s));
+                           M->layers(), ts, M->partial[1].as<float>(), (size_t)M->width * 32, 32, s));
   return PMC_OK;
 }
 

@@ -48,8 +48,9 @@ hipError_t mlp_loss(const float* yhat, const float* t, int n, int B, float inv_s
                     __bf16* dZt, double* part, double* acc, const TrainStep* ts, hipStream_t s);
 hipError_t mlp_sum_parts(const double* part, int64_t n, double* acc, hipStream_t s);
 // One layer's weight gradient g [rows][cols] from its 16 split-K partials
-// and bias gradient gb [rows_b] (row sums of dZt [rows_b][B]) in one
-// launch; with ts_next, the launch also advances the step record.
+// and bias gradient gb [rows_b] (row sums of dZt [rows_b][B]; rows_b = 0:
+// none) in one launch; with ts_next, the launch also advances the step
+// record.
 hipError_t mlp_layer_grads(const float* partial, int splits, size_t zstride, int ldp, int rows, int cols, float* g,
                            const __bf16* dZt, int B, int rows_b, float* gb, TrainStep* ts_next, hipStream_t s);
 // One launch of the backward pass that runs up to three independent jobs
@@ -72,14 +73,23 @@ struct MlpGradJob {
   float* g = nullptr;
   const __bf16* dZt = nullptr; int B = 0, rows_b = 0;
   float* gb = nullptr;
+  // optional: the bias gradient gb2 [rows_b2] of one more layer (row sums
+  // of dZt2 [rows_b2][B]), and the step record to advance
+  const __bf16* dZt2 = nullptr; int rows_b2 = 0;
+  float* gb2 = nullptr;
+  TrainStep* ts_next = nullptr;
 };
 hipError_t mlp_backward_step(const MlpGemmJob& back, const float* Z, __bf16* dZ, __bf16* dZt,
                              const MlpGemmJob& wgrad, int splits, float* wpart, int ldc, const MlpGradJob& red,
                              hipStream_t s);
 // Adam on the FP32 master parameters and the BF16 repack of the weights
-// (with ts: lr, c1, c2 from its current step).
+// (with ts: lr, c1, c2 from its current step).  With part1, the gradient of
+// layer 1's weights is the sum of its 16 split-K partials (part1
+// [16][rows][ldp1], zstride1 apart), taken here in the order
+// mlp_layer_grads takes it, instead of g.
 hipError_t mlp_adam_pack(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
-                         float eps, float c1, float c2, const MlpLayers& L, const TrainStep* ts, hipStream_t s);
+                         float eps, float c1, float c2, const MlpLayers& L, const TrainStep* ts,
+                         const float* part1, size_t zstride1, int ldp1, hipStream_t s);
 // W [out_pad][in_pad], Wt [in_pad][out_pad] and the fragment-ordered Wf
 // (A-operand fragments of 32-row output tiles and 16-wide k steps, each
 // 64 lanes x 16 bytes, tile-major) from the FP32 master weights.

@@ -313,13 +313,31 @@ __global__ void k_sum_parts(const double* part, int n, double* out) {
   out[0] += s;
 }
 
+// Row sums of dZt [rows_b][B] into gb: block bid covers rows 4 bid .. + 3,
+// one wave per row (lane l sums elements 8 (l + 64 i) .. + 7 for i = 0, 1,
+// .. with 16-byte loads, B a multiple of 8; then a butterfly).
+__device__ __forceinline__ void bias_rows_block(const __bf16* __restrict__ dZt, int B, int rows_b,
+                                                float* __restrict__ gb, int bid) {
+  const int lane = threadIdx.x & 63;
+  const int r = bid * 4 + (threadIdx.x >> 6);
+  if (r >= rows_b) return;
+  const __bf16* p = dZt + (size_t)r * B;
+  float sum = 0.0f;
+  for (int b = 8 * lane; b < B; b += 512) {
+    const bf16x8 v = *reinterpret_cast<const bf16x8*>(p + b);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sum += from_bf16(v[j]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+  if (lane == 0) gb[r] = sum;
+}
+
 // The weight and bias gradients of one layer in one launch.  Blocks
 // [0, n_red) reduce the split-K partials: g[row][col] (rows < rows_real,
 // cols < cols_real, row-major with ld cols_real) = the sum over the SPLITS
-// partials partial[z][row][col] (ld ldp) in z order.  The other blocks sum
-// rows of dZt (BF16 [rows_b][B]) into gb, one wave per row: lane l sums
-// elements 8 (l + 64 i) .. + 7 for i = 0, 1, .. (16-byte loads, B a multiple
-// of 8), then the lanes' sums are added by a butterfly.  With a step
+// partials partial[z][row][col] (ld ldp) in z order from 0.  The other
+// blocks sum the rows of dZt (BF16 [rows_b][B]) into gb.  With a step
 // record, block 0 also advances it: this launch is the last of a step's
 // gradients, and nothing in it reads the record.
 template <int SPLITS>
@@ -341,19 +359,7 @@ __device__ __forceinline__ void layer_grads_block(const float* __restrict__ part
     g[i] = sum;
     return;
   }
-  const int lane = threadIdx.x & 63;
-  const int r = (bid - n_red) * 4 + (threadIdx.x >> 6);
-  if (r >= rows_b) return;
-  const __bf16* p = dZt + (size_t)r * B;
-  float sum = 0.0f;
-  for (int b = 8 * lane; b < B; b += 512) {
-    const bf16x8 v = *reinterpret_cast<const bf16x8*>(p + b);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) sum += from_bf16(v[j]);
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
-  if (lane == 0) gb[r] = sum;
+  bias_rows_block(dZt, B, rows_b, gb, bid - n_red);
 }
 template <int SPLITS>
 __global__ __launch_bounds__(256) void k_layer_grads(const float* __restrict__ partial, size_t zstride, int ldp,
@@ -365,9 +371,11 @@ __global__ __launch_bounds__(256) void k_layer_grads(const float* __restrict__ p
                             (int)blockIdx.x);
 }
 
-// A backward launch's three jobs over one flat grid: blocks [0, nb) the
+// A backward launch's jobs over one flat grid: blocks [0, nb) the
 // back-propagation GEMM, then nw blocks of the weight-gradient GEMM, then
-// the reduction's blocks (a count of 0 leaves a job out).  The jobs share
+// the reduction's blocks, then those of one more layer's bias sums (a
+// count of 0 leaves a job out); the reduction's first block advances the
+// step record when one is given.  The jobs share
 // no outputs, and no block waits on another (a block's barriers are its
 // own, every thread of it on the same job).
 struct GemmGrid {
@@ -377,6 +385,8 @@ struct GemmGrid {
 struct RedGrid {
   const float* partial; size_t zstride; int ldp, rows, cols; float* g; const __bf16* dZt; int B, rows_b;
   float* gb; int n_red, blocks;
+  const __bf16* dZt2; int rows_b2; float* gb2; int blocks2;   // one more layer's bias sums
+  TrainStep* ts_next;
 };
 __global__ __launch_bounds__(256) void k_backward_step(GemmGrid bj, EpiBackHidden be, GemmGrid wj, EpiF32 we,
                                                        RedGrid rj) {
@@ -396,9 +406,14 @@ __global__ __launch_bounds__(256) void k_backward_step(GemmGrid bj, EpiBackHidde
     return;
   }
   b -= nw;
-  if (b < rj.blocks)
+  if (b < rj.blocks) {
+    if (rj.ts_next && b == 0 && threadIdx.x == 0) rj.ts_next->step += 1;
     layer_grads_block<16>(rj.partial, rj.zstride, rj.ldp, rj.rows, rj.cols, rj.g, rj.dZt, rj.B, rj.rows_b, rj.gb,
                           rj.n_red, b);
+    return;
+  }
+  b -= rj.blocks;
+  if (b < rj.blocks2) bias_rows_block(rj.dZt2, rj.B, rj.rows_b2, rj.gb2, b);
 }
 
 // One Adam step on the FP32 master parameters followed by the BF16 copies
@@ -409,14 +424,29 @@ __global__ __launch_bounds__(256) void k_backward_step(GemmGrid bj, EpiBackHidde
 // already advanced the record, so that step is step - 1.
 __global__ void k_adam_pack(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
                             const float* __restrict__ g, int64_t n, float lr, float b1, float b2, float eps,
-                            float c1, float c2, MlpLayers L, const TrainStep* __restrict__ ts) {
+                            float c1, float c2, MlpLayers L, const TrainStep* __restrict__ ts,
+                            const float* __restrict__ part1, size_t zstride1, int ldp1) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (ts) {
     const float* h = ts->hyper + 3 * (ts->step - 1);
     lr = h[0]; c1 = h[1]; c2 = h[2];
   }
-  const float gi = g[i];
+  float gi;
+  if (part1 && i >= L.oW[0] && i < L.ob[0]) {
+    // layer 1's weight gradient from its split-K partials, summed in z
+    // order from 0 as the reduction of the other layers sums them
+    const int64_t j = i - L.oW[0];
+    const float* p = part1 + (size_t)(j / L.in[0]) * ldp1 + (j % L.in[0]);
+    float pv[16];
+#pragma unroll
+    for (int z = 0; z < 16; ++z) pv[z] = p[z * zstride1];
+    gi = 0.0f;
+#pragma unroll
+    for (int z = 0; z < 16; ++z) gi += pv[z];
+  } else {
+    gi = g[i];
+  }
   const float mi = b1 * m[i] + (1.0f - b1) * gi;
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
@@ -625,7 +655,7 @@ hipError_t mlp_sum_parts(const double* part, int64_t n, double* acc, hipStream_t
 }
 hipError_t mlp_layer_grads(const float* partial, int splits, size_t zstride, int ldp, int rows, int cols, float* g,
                            const __bf16* dZt, int B, int rows_b, float* gb, TrainStep* ts_next, hipStream_t s) {
-  if (splits != 16 || B % 8 || rows < 1 || cols < 1 || rows_b < 1) return hipErrorInvalidValue;
+  if (splits != 16 || B % 8 || rows < 1 || cols < 1 || rows_b < 0) return hipErrorInvalidValue;
   const int n_red = (rows * cols + 255) / 256;
   hipLaunchKernelGGL(k_layer_grads<16>, dim3(n_red + (rows_b + 3) / 4), dim3(256), 0, s, partial, zstride, ldp, rows,
                      cols, g, dZt, B, rows_b, gb, n_red, ts_next);
@@ -657,14 +687,21 @@ hipError_t mlp_backward_step(const MlpGemmJob& back, const float* Z, __bf16* dZ,
   if (!gemm_grid(back, 1, bj) || !gemm_grid(wgrad, splits, wj)) return hipErrorInvalidValue;
   if (back.M && (!Z || !dZ || !dZt)) return hipErrorInvalidValue;
   if (wgrad.M && (!wpart || ldc < wgrad.N)) return hipErrorInvalidValue;
-  RedGrid rj{red.partial, red.zstride, red.ldp, red.rows, red.cols, red.g, red.dZt, red.B, red.rows_b, red.gb, 0, 0};
+  RedGrid rj{red.partial, red.zstride, red.ldp, red.rows, red.cols, red.g, red.dZt, red.B, red.rows_b, red.gb, 0, 0,
+             red.dZt2, red.rows_b2, red.gb2, 0, red.ts_next};
   if (red.rows) {
     if (red.rows < 1 || red.cols < 1 || red.rows_b < 1 || red.B % 8 || !red.partial || !red.g || !red.dZt || !red.gb)
       return hipErrorInvalidValue;
     rj.n_red = (red.rows * red.cols + 255) / 256;
     rj.blocks = rj.n_red + (red.rows_b + 3) / 4;
+    if (red.rows_b2) {
+      if (red.rows_b2 < 0 || !red.dZt2 || !red.gb2) return hipErrorInvalidValue;
+      rj.blocks2 = (red.rows_b2 + 3) / 4;
+    }
+  } else if (red.rows_b2 || red.ts_next) {
+    return hipErrorInvalidValue;
   }
-  const int64_t total = (int64_t)bj.gx * bj.gy * bj.gz + (int64_t)wj.gx * wj.gy * wj.gz + rj.blocks;
+  const int64_t total = (int64_t)bj.gx * bj.gy * bj.gz + (int64_t)wj.gx * wj.gy * wj.gz + rj.blocks + rj.blocks2;
   if (total < 1 || total > INT32_MAX) return hipErrorInvalidValue;
   const EpiBackHidden be{Z, back.N, dZ, back.N, dZt, back.M};
   const EpiF32 we{wpart, ldc, (size_t)wgrad.M * ldc};
@@ -672,9 +709,10 @@ hipError_t mlp_backward_step(const MlpGemmJob& back, const float* Z, __bf16* dZ,
   return hipGetLastError();
 }
 hipError_t mlp_adam_pack(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
-                         float eps, float c1, float c2, const MlpLayers& L, const TrainStep* ts, hipStream_t s) {
+                         float eps, float c1, float c2, const MlpLayers& L, const TrainStep* ts,
+                         const float* part1, size_t zstride1, int ldp1, hipStream_t s) {
   hipLaunchKernelGGL(k_adam_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps,
-                     c1, c2, L, ts);
+                     c1, c2, L, ts, part1, zstride1, ldp1);
   return hipGetLastError();
 }
 hipError_t mlp_infer256(const float* x, int n, int n_in, const float* lohi, const __bf16* W1, const float* b1,
