@@ -1466,10 +1466,14 @@ extern "C" int pmc_price_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch*
     lanes = it->second.lanes;
   } else {
     // untuned: enough paths per thread to keep the item count (and the
-    // partial-sum buffer) below 2^22
+    // partial-sum buffer) below 2^22 at one path per lane, and two paths
+    // per lane where paths are streamed (the launch falls back to one
+    // otherwise; with one, the batched down-and-out headline ran 1.36x
+    // longer)
     while (ppt < 1024 && (uint64_t)b->n_inst * ((o->n_paths + (uint64_t)block * ppt - 1) / ((uint64_t)block * ppt)) >
                              (1ull << 22))
       ppt *= 2;
+    if (!o->block && o->n_paths >= (uint64_t)block * 2) lanes = 2;
   }
   // A call identical to the previous batch, with the tables and buffers
   // untouched since: its plan (and graph) serve again; the kernels all run.
