@@ -1295,6 +1295,26 @@ int batch_prepare(pmc_ctx* c, const pmc_payoff* p, const pmc_batch* b, const pmc
     stream = streamable(p, it->first.data(), o->history ? o->t_now : 0);
   const uint64_t N = o->n_paths;
   if (!stream || N < (uint64_t)lanes) lanes = 1;
+  if (ppt == 0) {
+    // untuned: enough paths per thread to keep the item count (and the
+    // partial-sum buffer) below 2^22, and for short paths enough that a
+    // thread's tile simulates at least 128 asset-dates (per-tile set-up and
+    // sums otherwise dominate: the surrogate's label batches, 3 assets and
+    // at most 5 dates, took 52 ms per chunk at 2 paths per thread and 36.6 at
+    // 16), while each instance keeps at least 8 tiles and the batch at
+    // least 8 items per CU
+    ppt = 1;
+    while (ppt < 1024 && (uint64_t)I * ((N + (uint64_t)block * ppt - 1) / ((uint64_t)block * ppt)) > (1ull << 22))
+      ppt *= 2;
+    const int64_t dims = std::max<int64_t>(1, tb.max_dims);
+    for (;;) {
+      const uint64_t next_tile = (uint64_t)block * lanes * ppt * 2;
+      if (ppt >= 1024 || (int64_t)ppt * dims >= 128 || N < next_tile * 8 ||
+          (uint64_t)I * (N / next_tile) < 8ull * (uint64_t)std::max(1, c->n_cu))
+        break;
+      ppt *= 2;
+    }
+  }
   // work items (instance, tile), instances with the most slots first; the
   // item list is implicit: item i is tile i % tiles of instance order[i / tiles]
   const uint32_t tile_paths = (uint32_t)block * (uint32_t)ppt * (uint32_t)lanes;
@@ -1465,14 +1485,11 @@ extern "C" int pmc_price_batch(pmc_ctx* c, const pmc_payoff* p, const pmc_batch*
     ppt = it->second.ppt;
     lanes = it->second.lanes;
   } else {
-    // untuned: enough paths per thread to keep the item count (and the
-    // partial-sum buffer) below 2^22 at one path per lane, and two paths
-    // per lane where paths are streamed (the launch falls back to one
-    // otherwise; with one, the batched down-and-out headline ran 1.36x
-    // longer)
-    while (ppt < 1024 && (uint64_t)b->n_inst * ((o->n_paths + (uint64_t)block * ppt - 1) / ((uint64_t)block * ppt)) >
-                             (1ull << 22))
-      ppt *= 2;
+    // untuned: the paths per thread are chosen with the batch's tables
+    // (ppt 0), and two paths per lane where paths are streamed (the launch
+    // falls back to one otherwise; with one, the batched down-and-out
+    // headline ran 1.36x longer)
+    ppt = 0;
     if (!o->block && o->n_paths >= (uint64_t)block * 2) lanes = 2;
   }
   // A call identical to the previous batch, with the tables and buffers
