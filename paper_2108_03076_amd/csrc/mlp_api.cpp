@@ -143,8 +143,11 @@ int forward(pmc_mlp* M, const float* x, int n, int B, bool train, const TrainSte
     in = M->H[l].as<__bf16>();
     ld = W;
   }
-  MLP_TRY(M, mlp_gemm_out(B, 32, W, in, W, M->W[3].as<__bf16>(), W, w + M->ob[3], M->Y.as<float>(),
-                          train ? 1.0f : (float)M->y_scale, s));
+  // (a training step's output layer runs with its loss gradient, first in
+  // backward())
+  if (!train)
+    MLP_TRY(M, mlp_gemm_out(B, 32, W, in, W, M->W[3].as<__bf16>(), W, w + M->ob[3], M->Y.as<float>(),
+                            (float)M->y_scale, s));
   return PMC_OK;
 }
 
@@ -157,40 +160,54 @@ int backward(pmc_mlp* M, const float* y, int n, int B, TrainStep* ts = nullptr) 
   hipStream_t s = stream_of(M);
   const int W = M->width;
   float* g = M->grad.as<float>();
-  MLP_TRY(M, mlp_loss(M->Y.as<float>(), y, n, B, (float)(1.0 / M->y_scale), 2.0f / (float)n,
-                      M->dZ4.as<__bf16>(), M->dZ4t.as<__bf16>(),
-                      ts ? M->part_epoch.as<double>() : M->part_loss.as<double>(), M->loss_acc.as<double>(), ts, s));
-  // Four launches after the loss.  Each back-propagates to the layer below
-  // (`back`, but the last), forms the split-K weight-gradient partials of
-  // the layer whose dZ it reads (`wgrad`) and reduces the previous launch's
-  // partials with that layer's bias sums (`red`, but the first); the
-  // partials alternate between two buffers.  The last also sums layer 1's
-  // bias gradient and advances the step record; layer 1's weight partials
-  // are summed by Adam in a training step (in the same order), and by one
-  // more launch otherwise.
+  const float inv_scale = (float)(1.0 / M->y_scale);
+  // output layer: yhat, and its gradient dZ4 = 2 (yhat - y / y_scale) / n
+  MLP_TRY(M, mlp_gemm_out_train(B, W, M->H[2].as<__bf16>(), W, M->W[3].as<__bf16>(), W,
+                                M->master.as<float>() + M->ob[3], M->Y.as<float>(), y, n, inv_scale, 2.0f / (float)n,
+                                M->dZ4.as<__bf16>(), M->dZ4t.as<__bf16>(), ts, s));
+  MlpLossJob loss;
+  loss.y = M->Y.as<float>();
+  loss.t = y;
+  loss.ts = ts;
+  loss.n = n;
+  loss.B = B;
+  loss.inv_scale = inv_scale;
+  loss.part = ts ? M->part_epoch.as<double>() : M->part_loss.as<double>();
+  // Four launches after the output layer.  Each back-propagates to the
+  // layer below (`back`, but the last), forms the split-K weight-gradient
+  // partials of the layer whose dZ it reads (`wgrad`) and reduces the
+  // previous launch's partials with that layer's bias sums (`red`, but the
+  // first); the partials alternate between two buffers.  The first also
+  // sums the batch's loss partials; the last also sums layer 1's bias
+  // gradient and advances the step record (the loss partials have read
+  // it); layer 1's weight partials are summed by Adam in a training step
+  // (in the same order), and by one more launch otherwise.
   float* pa = M->partial[0].as<float>();
   float* pb = M->partial[1].as<float>();
   const MlpGemmJob none;
   const MlpGradJob no_red;
+  const MlpLossJob no_loss;
   // layer 4: dW4 partials (dZ4^T H3), dZ3 = (dZ4 W4) * gelu'(Z3)
   MLP_TRY(M, mlp_backward_step(MlpGemmJob{B, W, 32, M->dZ4.as<__bf16>(), 32, M->Wt[3].as<__bf16>(), 32},
                                M->Z[2].as<float>(), M->dZ[2].as<__bf16>(), M->dZt[2].as<__bf16>(),
                                MlpGemmJob{32, W, B, M->dZ4t.as<__bf16>(), B, M->Ht[2].as<__bf16>(), B}, kSplits, pa,
-                               W, no_red, s));
+                               W, no_red, loss, s));
+  // without a step record: the batch's squared errors go to loss_acc
+  if (!ts) MLP_TRY(M, mlp_sum_parts(M->part_loss.as<double>(), (B + 255) / 256, M->loss_acc.as<double>(), s));
   // layer 3 and dZ2; dW4 and db4
   MLP_TRY(M, mlp_backward_step(MlpGemmJob{B, W, W, M->dZ[2].as<__bf16>(), W, M->Wt[2].as<__bf16>(), W},
                                M->Z[1].as<float>(), M->dZ[1].as<__bf16>(), M->dZt[1].as<__bf16>(),
                                MlpGemmJob{W, W, B, M->dZt[2].as<__bf16>(), B, M->Ht[1].as<__bf16>(), B}, kSplits, pb,
                                W, MlpGradJob{pa, (size_t)32 * W, W, 1, W, g + M->oW[3], M->dZ4t.as<__bf16>(), B, 1,
                                              g + M->ob[3]},
-                               s));
+                               no_loss, s));
   // layer 2 and dZ1; dW3 and db3
   MLP_TRY(M, mlp_backward_step(MlpGemmJob{B, W, W, M->dZ[1].as<__bf16>(), W, M->Wt[1].as<__bf16>(), W},
                                M->Z[0].as<float>(), M->dZ[0].as<__bf16>(), M->dZt[0].as<__bf16>(),
                                MlpGemmJob{W, W, B, M->dZt[1].as<__bf16>(), B, M->Ht[0].as<__bf16>(), B}, kSplits, pa,
                                W, MlpGradJob{pb, (size_t)W * W, W, W, W, g + M->oW[2], M->dZt[2].as<__bf16>(), B, W,
                                              g + M->ob[2]},
-                               s));
+                               no_loss, s));
   // layer 1 (X^T has 32 padded rows); dW2 and db2; db1; the step record
   // advances (the loss has read it)
   MlpGradJob red2{pa, (size_t)W * W, W, W, W, g + M->oW[1], M->dZt[1].as<__bf16>(), B, W, g + M->ob[1]};
@@ -200,7 +217,7 @@ int backward(pmc_mlp* M, const float* y, int n, int B, TrainStep* ts = nullptr) 
   red2.ts_next = ts;
   MLP_TRY(M, mlp_backward_step(none, nullptr, nullptr, nullptr,
                                MlpGemmJob{W, 32, B, M->dZt[0].as<__bf16>(), B, M->Xt.as<__bf16>(), B}, kSplits, pb,
-                               32, red2, s));
+                               32, red2, no_loss, s));
   // dW1: in a training step, Adam sums its partials itself; otherwise here
   if (!ts)
     MLP_TRY(M, mlp_layer_grads(pb, kSplits, (size_t)W * 32, 32, W, M->n_in, g + M->oW[0], nullptr, B, 0, nullptr,

@@ -38,14 +38,15 @@ hipError_t mlp_gemm_out(int M, int N, int K, const __bf16* A, int lda, const __b
 // x raw inputs [n][n_in] (or, with ts, the step record's batch).
 hipError_t mlp_scale_inputs(const float* x, int n, int n_in, const float* lo, const float* hi, int B, __bf16* X,
                             __bf16* Xt, const TrainStep* ts, hipStream_t s);
-// t targets [n] (or, with ts, the step record's batch).
-// Loss partials and the output layer's gradient dZ (and dZ^T) from yhat
-// and the targets t [n] (or, with ts, the step record's batch).  Without a
-// step record the batch's squared errors are added to acc; with one, each
-// block's partial goes to part[step * blocks + block] and mlp_sum_parts
-// adds a whole pass's partials at its end.
-hipError_t mlp_loss(const float* yhat, const float* t, int n, int B, float inv_scale, float grad_scale, __bf16* dZ,
-                    __bf16* dZt, double* part, double* acc, const TrainStep* ts, hipStream_t s);
+// Output layer of a training step (N = 32 padded outputs, column 0 real):
+// yhat = bias[0] + (A Bt^T)[row][0] into y [M], and the output gradient
+// d = grad_scale (yhat - t inv_scale) (0 for rows >= n) as column 0 of dZ
+// [M][32] and row 0 of dZt [32][M], every other element of both 0; t the
+// targets [n] or, with ts, the step record's batch.
+hipError_t mlp_gemm_out_train(int M, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb, const float* bias,
+                              float* y, const float* t, int n, float inv_scale, float grad_scale, __bf16* dZ,
+                              __bf16* dZt, const TrainStep* ts, hipStream_t s);
+// Adds part[0 .. n) in order to acc[0] (one thread).
 hipError_t mlp_sum_parts(const double* part, int64_t n, double* acc, hipStream_t s);
 // One layer's weight gradient g [rows][cols] from its 16 split-K partials
 // and bias gradient gb [rows_b] (row sums of dZt [rows_b][B]; rows_b = 0:
@@ -53,14 +54,15 @@ hipError_t mlp_sum_parts(const double* part, int64_t n, double* acc, hipStream_t
 // record.
 hipError_t mlp_layer_grads(const float* partial, int splits, size_t zstride, int ldp, int rows, int cols, float* g,
                            const __bf16* dZt, int B, int rows_b, float* gb, TrainStep* ts_next, hipStream_t s);
-// One launch of the backward pass that runs up to three independent jobs
+// One launch of the backward pass that runs up to four independent jobs
 // side by side (a job with no rows is left out):
 //  * back: back-propagation to the layer below, dZ = (A Bt^T) * gelu'(Z)
 //    (BF16 [M][N]) and dZ^T ([N][M]), Z FP32 [M][N];
 //  * wgrad: a layer's weight gradient A Bt^T as `splits` partial products
 //    over chunks of K, into wpart [splits][M][ldc];
 //  * red: another layer's weight and bias gradients from its partials, as
-//    mlp_layer_grads (without a step record).
+//    mlp_layer_grads (its step record advanced by its first block);
+//  * loss: the batch's loss partials (MlpLossJob below).
 // The jobs must not share outputs: red reads a partials buffer that wgrad
 // does not write; no job reads another job's output.
 struct MlpGemmJob {
@@ -79,9 +81,16 @@ struct MlpGradJob {
   float* gb2 = nullptr;
   TrainStep* ts_next = nullptr;
 };
+// loss: the batch's squared errors of the scaled targets, (y - t
+// inv_scale)^2 for rows < n in FP64, summed per block of 256 rows into
+// part[(ts ? step * blocks : 0) + block] (B = 0: no such job).
+struct MlpLossJob {
+  const float* y = nullptr; const float* t = nullptr; const TrainStep* ts = nullptr;
+  int n = 0, B = 0; float inv_scale = 1.0f; double* part = nullptr;
+};
 hipError_t mlp_backward_step(const MlpGemmJob& back, const float* Z, __bf16* dZ, __bf16* dZt,
                              const MlpGemmJob& wgrad, int splits, float* wpart, int ldc, const MlpGradJob& red,
-                             hipStream_t s);
+                             const MlpLossJob& loss, hipStream_t s);
 // Adam on the FP32 master parameters and the BF16 repack of the weights
 // (with ts: lr, c1, c2 from its current step).  With part1, the gradient of
 // layer 1's weights is the sum of its 16 split-K partials (part1

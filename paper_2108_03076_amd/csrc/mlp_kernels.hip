@@ -215,6 +215,37 @@ struct EpiOut {          // y = (b + v) * scale for output column 0
   }
 };
 
+// Output layer of a training step: yhat = b + v for output column 0 into y,
+// and the output gradient d = grad_scale (yhat - t inv_scale) (0 for rows
+// >= n, t the targets or the step record's batch) as column 0 of dZ
+// [rows][32] and row 0 of dZt [32][B], every other element of both 0.
+struct EpiOutTrain {
+  static constexpr bool kTransposed = true;
+  const float* bias; float* y; const float* t; const TrainStep* ts; int n, B; float inv_scale, grad_scale;
+  __bf16* dZ; __bf16* dZt;
+  __device__ float init(int col) const { return col == 0 ? bias[0] : 0.0f; }
+  __device__ __bf16 operator()(int row, int col, float v, int) const {
+    float d = 0.0f;
+    if (col == 0) {
+      y[row] = v;
+      if (row < n) {
+        const float* tt = ts ? ts->y + ts->step * (int64_t)B : t;
+        const float e = v - tt[row] * inv_scale;
+        d = grad_scale * e;
+      }
+    }
+    const __bf16 b = to_bf16(d);
+    dZ[(size_t)row * 32 + col] = b;
+    return b;
+  }
+  // dZt[col][row .. row + 15]
+  __device__ void store_t(int col, int row, bf16x8 v0, bf16x8 v1) const {
+    bf16x8* p = reinterpret_cast<bf16x8*>(dZt + (size_t)col * B + row);
+    p[0] = v0;
+    p[1] = v1;
+  }
+};
+
 struct EpiBackHidden {   // dZ = dH * gelu'(Z) (BF16) and its transpose
   static constexpr bool kTransposed = true;
   const float* Z; int ldz; __bf16* dZ; int lddz; __bf16* dZt; int lddzt;
@@ -265,44 +296,6 @@ __global__ void k_scale_inputs(const float* __restrict__ x, int n, int n_in, con
   bf16x8* px = reinterpret_cast<bf16x8*>(X + (size_t)i * 16);
   px[0] = row[0];
   px[1] = row[1];
-}
-
-// dy = 2 (yhat - t) / n_total for real rows (0 for padding), stored as the
-// first column of dZ4 [B][32] and first row of dZ4t [32][B]; per-block sums
-// of (yhat - t)^2 into part[block].
-// With a step record, t is its batch of the current step instead.
-__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ yhat, const float* __restrict__ t, int n,
-                                              int B, float inv_scale, float grad_scale, __bf16* __restrict__ dZ,
-                                              __bf16* __restrict__ dZt, double* __restrict__ part,
-                                              const TrainStep* __restrict__ ts) {
-  __shared__ double red[256];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ts) t = ts->y + ts->step * (int64_t)B;
-  double l = 0.0;
-  if (i < B) {
-    float d = 0.0f;
-    if (i < n) {
-      const float e = yhat[i] - t[i] * inv_scale;
-      l = (double)e * (double)e;
-      d = grad_scale * e;
-    }
-    const __bf16 b = to_bf16(d);
-    bf16x8 first, zero;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) { first[j] = to_bf16(0.0f); zero[j] = to_bf16(0.0f); }
-    first[0] = b;
-    bf16x8* pz = reinterpret_cast<bf16x8*>(dZ + (size_t)i * 32);
-    pz[0] = first; pz[1] = zero; pz[2] = zero; pz[3] = zero;
-    for (int j = 0; j < 32; ++j) dZt[(size_t)j * B + i] = j == 0 ? b : to_bf16(0.0f);
-  }
-  red[threadIdx.x] = l;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  // with a step record: one slot per (step, block), summed once per pass
-  if (threadIdx.x == 0) part[(ts ? ts->step * (int64_t)gridDim.x : 0) + blockIdx.x] = red[0];
 }
 
 // out[0] += sum of part[0..n) in a fixed order (one thread).
@@ -371,13 +364,36 @@ __global__ __launch_bounds__(256) void k_layer_grads(const float* __restrict__ p
                             (int)blockIdx.x);
 }
 
+// The squared errors of a training batch summed per block of 256 rows,
+// (yhat - t inv_scale)^2 in FP64 for rows < n, by a fixed tree over the
+// block: part[(ts ? step * blocks : 0) + block].
+struct LossGrid {
+  const float* y; const float* t; const TrainStep* ts; int n, B; float inv_scale; double* part; int blocks;
+};
+__device__ __forceinline__ void loss_part_block(const LossGrid& lj, int bid, double* red) {
+  const int i = bid * 256 + (int)threadIdx.x;
+  double l = 0.0;
+  if (i < lj.B && i < lj.n) {
+    const float* tt = lj.ts ? lj.ts->y + lj.ts->step * (int64_t)lj.B : lj.t;
+    const float e = lj.y[i] - tt[i] * lj.inv_scale;
+    l = (double)e * (double)e;
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) lj.part[(lj.ts ? lj.ts->step * (int64_t)lj.blocks : 0) + bid] = red[0];
+}
+
 // A backward launch's jobs over one flat grid: blocks [0, nb) the
 // back-propagation GEMM, then nw blocks of the weight-gradient GEMM, then
 // the reduction's blocks, then those of one more layer's bias sums (a
-// count of 0 leaves a job out); the reduction's first block advances the
-// step record when one is given.  The jobs share
-// no outputs, and no block waits on another (a block's barriers are its
-// own, every thread of it on the same job).
+// count of 0 leaves a job out), then those of the loss partials; the
+// reduction's first block advances the step record when one is given.  The
+// jobs share no outputs, and no block waits on another (a block's barriers
+// are its own, every thread of it on the same job).
 struct GemmGrid {
   int M, N, K; const __bf16* A; int lda; const __bf16* Bt; int ldb; int k_chunk; int gx, gy, gz;
   __device__ int blocks() const { return gx * gy * gz; }
@@ -389,7 +405,7 @@ struct RedGrid {
   TrainStep* ts_next;
 };
 __global__ __launch_bounds__(256) void k_backward_step(GemmGrid bj, EpiBackHidden be, GemmGrid wj, EpiF32 we,
-                                                       RedGrid rj) {
+                                                       RedGrid rj, LossGrid lj) {
   __shared__ __bf16 lds[kGemmLds];
   int b = blockIdx.x;
   const int nb = bj.blocks();
@@ -413,7 +429,12 @@ __global__ __launch_bounds__(256) void k_backward_step(GemmGrid bj, EpiBackHidde
     return;
   }
   b -= rj.blocks;
-  if (b < rj.blocks2) bias_rows_block(rj.dZt2, rj.B, rj.rows_b2, rj.gb2, b);
+  if (b < rj.blocks2) {
+    bias_rows_block(rj.dZt2, rj.B, rj.rows_b2, rj.gb2, b);
+    return;
+  }
+  b -= rj.blocks2;
+  if (b < lj.blocks) loss_part_block(lj, b, reinterpret_cast<double*>(lds));
 }
 
 // One Adam step on the FP32 master parameters followed by the BF16 copies
@@ -640,13 +661,11 @@ hipError_t mlp_scale_inputs(const float* x, int n, int n_in, const float* lo, co
   hipLaunchKernelGGL(k_scale_inputs, dim3((B + 255) / 256), dim3(256), 0, s, x, n, n_in, lo, hi, B, X, Xt, ts);
   return hipGetLastError();
 }
-hipError_t mlp_loss(const float* yhat, const float* t, int n, int B, float inv_scale, float grad_scale, __bf16* dZ,
-                    __bf16* dZt, double* part, double* acc, const TrainStep* ts, hipStream_t s) {
-  const int blocks = (B + 255) / 256;
-  hipLaunchKernelGGL(k_loss, dim3(blocks), dim3(256), 0, s, yhat, t, n, B, inv_scale, grad_scale, dZ, dZt, part,
-                     ts);
-  if (!ts) hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part, blocks, acc);
-  return hipGetLastError();
+hipError_t mlp_gemm_out_train(int M, int K, const __bf16* A, int lda, const __bf16* Bt, int ldb, const float* bias,
+                              float* y, const float* t, int n, float inv_scale, float grad_scale, __bf16* dZ,
+                              __bf16* dZt, const TrainStep* ts, hipStream_t s) {
+  if (!ts && !t) return hipErrorInvalidValue;
+  return gemm(M, 32, K, A, lda, Bt, ldb, 1, EpiOutTrain{bias, y, t, ts, n, M, inv_scale, grad_scale, dZ, dZt}, s);
 }
 hipError_t mlp_sum_parts(const double* part, int64_t n, double* acc, hipStream_t s) {
   if (n < 1 || n > INT32_MAX) return hipErrorInvalidValue;
@@ -682,7 +701,7 @@ bool gemm_grid(const MlpGemmJob& j, int splits, GemmGrid& g) {
 
 hipError_t mlp_backward_step(const MlpGemmJob& back, const float* Z, __bf16* dZ, __bf16* dZt,
                              const MlpGemmJob& wgrad, int splits, float* wpart, int ldc, const MlpGradJob& red,
-                             hipStream_t s) {
+                             const MlpLossJob& loss, hipStream_t s) {
   GemmGrid bj, wj;
   if (!gemm_grid(back, 1, bj) || !gemm_grid(wgrad, splits, wj)) return hipErrorInvalidValue;
   if (back.M && (!Z || !dZ || !dZt)) return hipErrorInvalidValue;
@@ -701,11 +720,17 @@ hipError_t mlp_backward_step(const MlpGemmJob& back, const float* Z, __bf16* dZ,
   } else if (red.rows_b2 || red.ts_next) {
     return hipErrorInvalidValue;
   }
-  const int64_t total = (int64_t)bj.gx * bj.gy * bj.gz + (int64_t)wj.gx * wj.gy * wj.gz + rj.blocks + rj.blocks2;
+  LossGrid lj{loss.y, loss.t, loss.ts, loss.n, loss.B, loss.inv_scale, loss.part, 0};
+  if (loss.B) {
+    if (loss.B < 1 || loss.n < 0 || !loss.y || !loss.part || (!loss.t && !loss.ts)) return hipErrorInvalidValue;
+    lj.blocks = (loss.B + 255) / 256;
+  }
+  const int64_t total = (int64_t)bj.gx * bj.gy * bj.gz + (int64_t)wj.gx * wj.gy * wj.gz + rj.blocks + rj.blocks2 +
+                        lj.blocks;
   if (total < 1 || total > INT32_MAX) return hipErrorInvalidValue;
   const EpiBackHidden be{Z, back.N, dZ, back.N, dZt, back.M};
   const EpiF32 we{wpart, ldc, (size_t)wgrad.M * ldc};
-  hipLaunchKernelGGL(k_backward_step, dim3((unsigned)total), dim3(256), 0, s, bj, be, wj, we, rj);
+  hipLaunchKernelGGL(k_backward_step, dim3((unsigned)total), dim3(256), 0, s, bj, be, wj, we, rj, lj);
   return hipGetLastError();
 }
 hipError_t mlp_adam_pack(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
