@@ -193,3 +193,43 @@ def test_batch_graph_replays_follow_the_sobol_shape():
         out = P.price_batch(pay, tenv, np.zeros((2, 0)), **model_kw(cfg), **opts_kw(cfg, n))
         one = P.price(pay, cfg.tenv, [], **model_kw(cfg), **opts_kw(cfg, n))
         assert out[0]["sum"] == pytest.approx(one["sum"], rel=1e-12), n
+
+
+def test_untuned_tiles_price_the_same_paths(tmp_path):
+    """Without an autotuned tile a batch picks its own: two streamed paths
+    per lane for the down-and-out sample, and for the short paths of the
+    surrogate's worst-of family (3 assets, 1-5 dates, a model per point)
+    more paths per thread than the item count alone asks for.  Either way
+    each instance prices the same paths as at a forced one-path tile: the
+    sums agree up to their order.  (Fresh contexts: no tuned entry leaks
+    into the other tests.)"""
+    import paper_2108_03076_amd as P
+    from paper_2108_03076_amd import surrogate as S
+    inst, ids, T, KB = _sample()
+    c5 = W.C5
+    pts = W.c5_points(64, 77)
+    fb = S.family_batch(pts)
+    cases = [
+        ("down-and-out", CFG, T, KB, dict(**model_kw(CFG), **opts_kw(CFG, C4_SAMPLE_PATHS), instance_ids=ids)),
+        ("worst-of family", c5, fb["tenv"], fb["params"],
+         dict(spot=fb["spot"], vol=fb["vol"], corr=fb["corr"], per_instance_model=True, rate=c5.rate,
+              years_per_day=c5.years_per_day, n_paths=1 << 14, rng="philox", seed=42, precision="f32",
+              instance_ids=np.arange(64, dtype=np.uint32))),
+    ]
+
+    def payoff(cfg):
+        return P.Payoff(P.Context(0), cfg.il, cfg.asset_labels, cfg.param_labels, cfg.tvars)
+
+    for name, cfg, tenv, params, kw in cases:
+        print(f"[batch] untuned tile: {name}", flush=True)
+        untuned = P.price_batch(payoff(cfg), tenv, params, **kw)
+        cache = tmp_path / (name.replace(" ", "_") + ".txt")
+        P.autotune_batch(payoff(cfg), tenv, params, cache_path=str(cache), **kw)
+        key = _tune_key(cache)[0]
+        cache.write_text(f"{key} 256 1 1\n")
+        pay = payoff(cfg)
+        assert P.autotune_batch(pay, tenv, params, cache_path=str(cache), **kw) == (256, 1, 1)
+        forced = P.price_batch(pay, tenv, params, **kw)
+        for a, b in zip(untuned, forced):
+            assert a["path_dates"] == b["path_dates"]
+            assert a["sum"] == pytest.approx(b["sum"], rel=1e-12, abs=1e-9), name
