@@ -376,6 +376,11 @@ def main():
     def step():
         res = P.price_batch(pay4, tenv, params, **kw4)
         return res[0]["ms"], res
+    # set-up, whatever the warm-up count: the first calls at the tuned tile
+    # prepare its tables and capture and instantiate its graph, which later
+    # identical calls replay
+    step()
+    step()
     sec, outs = time_steps(step, args.steps, args.warmup)
     res = outs[-1][1]
     graph_ms = float(np.mean([o[0] for o in outs]))
