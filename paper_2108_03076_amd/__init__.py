@@ -11,7 +11,7 @@ and streams.
 """
 from ._lib import (EXPORTED, LIB_PATH, Context, PmcError, Payoff, autotune_batch, compile_contract, eval_paths,
                    gen_paths, load_contract,
-                   lib, load_payoff, price, price_batch, price_noalloc, risk_batch, Pricer, Surrogate)
+                   lib, load_payoff, price, price_batch, price_noalloc, risk_batch, Pricer, BatchPricer, Surrogate)
 
 __all__ = ["Context", "Payoff", "PmcError", "price", "price_batch", "price_noalloc", "risk_batch", "autotune_batch", "gen_paths",
-           "eval_paths", "load_payoff", "compile_contract", "load_contract", "Pricer", "Surrogate", "lib", "LIB_PATH", "EXPORTED"]
+           "eval_paths", "load_payoff", "compile_contract", "load_contract", "Pricer", "BatchPricer", "Surrogate", "lib", "LIB_PATH", "EXPORTED"]

@@ -546,6 +546,35 @@ def price_batch(payoff: Payoff, tenv, params, *, spot, vol, corr=None, rate=0.03
     return [r.as_dict() for r in out]
 
 
+class BatchPricer:
+    """A prepared pmc_price_batch call: the arguments are marshalled once
+    and each call runs one complete batched pricing through the C ABI,
+    leaving the raw results in `out` (for timing loops; `results()` turns
+    them into the dicts price_batch returns)."""
+
+    def __init__(self, payoff: Payoff, tenv, params, *, spot, vol, corr=None, rate=0.03, years_per_day=1.0,
+                 per_instance_model=False, instance_ids=None, **opts):
+        self.payoff = payoff
+        self.b, self.n, self._keep = _batch(payoff, tenv, params, spot, vol, corr, per_instance_model, instance_ids)
+        A = len(payoff.assets)
+        if per_instance_model:
+            self.g, self._keep2 = make_model([100.0] * A, [0.0] * A, None, rate, years_per_day)
+        else:
+            self.g, self._keep2 = make_model(spot, vol, corr, rate, years_per_day)
+        self.o = make_opts(**opts)
+        self.out = (Result * self.n)()
+        self._args = (payoff.ctx.h, payoff.h, C.byref(self.b), C.byref(self.g), C.byref(self.o), self.out)
+
+    def __call__(self):
+        st = lib.pmc_price_batch(*self._args)
+        if st != 0:
+            self.payoff.ctx.check(st)
+        return self.out
+
+    def results(self):
+        return [r.as_dict() for r in self.out]
+
+
 def risk_batch(payoff: Payoff, tenv, params, *, spot, vol, corr=None, rate=0.03, years_per_day=1.0,
                per_instance_model=False, instance_ids=None, rel_spot_bump=0.01, abs_vol_bump=0.01, **opts):
     """Bump-and-revalue Greeks of every instance on common random numbers

@@ -233,3 +233,19 @@ def test_untuned_tiles_price_the_same_paths(tmp_path):
         for a, b in zip(untuned, forced):
             assert a["path_dates"] == b["path_dates"]
             assert a["sum"] == pytest.approx(b["sum"], rel=1e-12, abs=1e-9), name
+
+
+def test_batch_pricer_equals_price_batch():
+    """The prepared batch call (arguments marshalled once, for timing loops)
+    returns what price_batch returns, call after call."""
+    import paper_2108_03076_amd as P
+    inst, ids, T, KB = _sample()
+    pay = gpu_payoff(CFG)
+    kw = dict(**model_kw(CFG), **opts_kw(CFG, C4_SAMPLE_PATHS), instance_ids=ids)
+    ref = P.price_batch(pay, T, KB, **kw)
+    pricer = P.BatchPricer(pay, T, KB, **kw)
+    for _ in range(3):
+        pricer()
+        got = pricer.results()
+        assert [(r["sum"], r["sum_sq"], r["path_dates"]) for r in got] == \
+            [(r["sum"], r["sum_sq"], r["path_dates"]) for r in ref]
