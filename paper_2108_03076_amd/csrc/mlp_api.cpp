@@ -129,8 +129,11 @@ int forward(pmc_mlp* M, const float* x, int n, int B, bool train, const TrainSte
   hipStream_t s = stream_of(M);
   const int W = M->width;
   const float* w = M->master.as<float>();
-  MLP_TRY(M, mlp_scale_inputs(x, n, M->n_in, M->lohi.as<float>(), M->lohi.as<float>() + 32, B,
-                              M->X.as<__bf16>(), M->Xt.as<__bf16>(), ts, s));
+  // (a training step's inputs were scaled by the previous step's Adam
+  // launch, or at the start of the pass)
+  if (!ts)
+    MLP_TRY(M, mlp_scale_inputs(x, n, M->n_in, M->lohi.as<float>(), M->lohi.as<float>() + 32, B,
+                                M->X.as<__bf16>(), M->Xt.as<__bf16>(), nullptr, s));
   const __bf16* in = M->X.as<__bf16>();
   int ld = 16;
   for (int l = 0; l < 3; ++l) {
@@ -403,9 +406,16 @@ int enqueue_step(pmc_mlp* M, const pmc_train_opts* o, int B, TrainStep* ts) {
   if (rc == PMC_OK) rc = backward(M, nullptr, B, B, ts);
   if (rc != PMC_OK) return rc;
   hipStream_t s = stream_of(M);
+  MlpNextInputs next;
+  next.lo = M->lohi.as<float>();
+  next.hi = M->lohi.as<float>() + 32;
+  next.n_in = M->n_in;
+  next.B = B;
+  next.X = M->X.as<__bf16>();
+  next.Xt = M->Xt.as<__bf16>();
   MLP_TRY(M, mlp_adam_pack(M->master.as<float>(), M->m.as<float>(), M->v.as<float>(), M->grad.as<float>(),
                            M->n_params, 0.0f, (float)o->beta1, (float)o->beta2, (float)o->eps, 1.0f, 1.0f,
-                           M->layers(), ts, M->partial[1].as<float>(), (size_t)M->width * 32, 32, s));
+                           M->layers(), ts, M->partial[1].as<float>(), (size_t)M->width * 32, 32, &next, s));
   return PMC_OK;
 }
 
@@ -480,11 +490,14 @@ extern "C" int pmc_mlp_train_epoch(pmc_mlp* m, const float* x, const float* y, i
   MLP_TRY(m, hipStreamSynchronize(s));
   m->hyper_host.resize((size_t)steps * 3);
   for (int64_t k = 0; k < steps; ++k) step_hyper(o, m->step + 1 + k, &m->hyper_host[(size_t)k * 3]);
-  m->tstep_host = TrainStep{x, y, m->hyper.as<float>(), 0};
+  m->tstep_host = TrainStep{x, y, m->hyper.as<float>(), 0, steps};
   MLP_TRY(m, hipMemcpyAsync(m->hyper.p, m->hyper_host.data(), m->hyper_host.size() * sizeof(float),
                             hipMemcpyHostToDevice, s));
   MLP_TRY(m, hipMemcpyAsync(m->tstep.p, &m->tstep_host, sizeof(TrainStep), hipMemcpyHostToDevice, s));
   MLP_TRY(m, hipMemsetAsync(m->loss_acc.p, 0, 8, s));
+  // the first step's scaled inputs (each step's Adam launch makes the next's)
+  MLP_TRY(m, mlp_scale_inputs(nullptr, B, m->n_in, m->lohi.as<float>(), m->lohi.as<float>() + 32, B,
+                              m->X.as<__bf16>(), m->Xt.as<__bf16>(), m->tstep.as<TrainStep>(), s));
   if (o->eager) {
     for (int64_t k = 0; k < steps; ++k) {
       rc = enqueue_step(m, o, B, m->tstep.as<TrainStep>());

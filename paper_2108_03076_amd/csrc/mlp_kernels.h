@@ -14,6 +14,15 @@ struct TrainStep {
   const float* y;
   const float* hyper;
   int64_t step;
+  int64_t n_steps;   // steps of the pass (the inputs of step n_steps do not exist)
+};
+// The scaled inputs of a training step's batch (X [B][16], Xt [32][B]
+// BF16, as mlp_scale_inputs makes them): with it, the Adam launch also
+// makes those of the step that follows (the step record has advanced),
+// if the pass has one.
+struct MlpNextInputs {
+  const float* lo = nullptr; const float* hi = nullptr; int n_in = 0, B = 0;
+  __bf16* X = nullptr; __bf16* Xt = nullptr;
 };
 
 // The four layers' places in the flat parameter vector and their BF16
@@ -98,7 +107,7 @@ hipError_t mlp_backward_step(const MlpGemmJob& back, const float* Z, __bf16* dZ,
 // mlp_layer_grads takes it, instead of g.
 hipError_t mlp_adam_pack(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
                          float eps, float c1, float c2, const MlpLayers& L, const TrainStep* ts,
-                         const float* part1, size_t zstride1, int ldp1, hipStream_t s);
+                         const float* part1, size_t zstride1, int ldp1, const MlpNextInputs* next, hipStream_t s);
 // W [out_pad][in_pad], Wt [in_pad][out_pad] and the fragment-ordered Wf
 // (A-operand fragments of 32-row output tiles and 16-wide k steps, each
 // 64 lanes x 16 bytes, tile-major) from the FP32 master weights.

@@ -278,12 +278,9 @@ hipError_t gemm(int M, int N, int K, const __bf16* A, int lda, const __bf16* Bt,
 // x raw [n][n_in] -> X [B][16] BF16 scaled to [-1,1] (columns >= n_in zero)
 // and its transpose Xt [32][B] (rows >= n_in zero).  Rows >= n are zero.
 // With a step record, x is its batch of the current step instead.
-__global__ void k_scale_inputs(const float* __restrict__ x, int n, int n_in, const float* __restrict__ lo,
-                               const float* __restrict__ hi, int B, __bf16* __restrict__ X,
-                               __bf16* __restrict__ Xt, const TrainStep* __restrict__ ts) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= B) return;
-  if (ts) x = ts->x + ts->step * (int64_t)B * n_in;
+__device__ __forceinline__ void scale_row(const float* __restrict__ x, int n, int n_in, const float* __restrict__ lo,
+                                          const float* __restrict__ hi, int B, __bf16* __restrict__ X,
+                                          __bf16* __restrict__ Xt, int i) {
   bf16x8 row[2];
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
@@ -296,6 +293,14 @@ __global__ void k_scale_inputs(const float* __restrict__ x, int n, int n_in, con
   bf16x8* px = reinterpret_cast<bf16x8*>(X + (size_t)i * 16);
   px[0] = row[0];
   px[1] = row[1];
+}
+__global__ void k_scale_inputs(const float* __restrict__ x, int n, int n_in, const float* __restrict__ lo,
+                               const float* __restrict__ hi, int B, __bf16* __restrict__ X,
+                               __bf16* __restrict__ Xt, const TrainStep* __restrict__ ts) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  if (ts) x = ts->x + ts->step * (int64_t)B * n_in;
+  scale_row(x, n, n_in, lo, hi, B, X, Xt, i);
 }
 
 // out[0] += sum of part[0..n) in a fixed order (one thread).
@@ -446,7 +451,17 @@ __global__ __launch_bounds__(256) void k_backward_step(GemmGrid bj, EpiBackHidde
 __global__ void k_adam_pack(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
                             const float* __restrict__ g, int64_t n, float lr, float b1, float b2, float eps,
                             float c1, float c2, MlpLayers L, const TrainStep* __restrict__ ts,
-                            const float* __restrict__ part1, size_t zstride1, int ldp1) {
+                            const float* __restrict__ part1, size_t zstride1, int ldp1, MlpNextInputs next,
+                            int adam_blocks) {
+  if ((int)blockIdx.x >= adam_blocks) {
+    // the next step's scaled inputs (the record has advanced to it), if
+    // the pass has one
+    const int r = ((int)blockIdx.x - adam_blocks) * (int)blockDim.x + (int)threadIdx.x;
+    if (r < next.B && ts->step < ts->n_steps)
+      scale_row(ts->x + ts->step * (int64_t)next.B * next.n_in, next.B, next.n_in, next.lo, next.hi, next.B, next.X,
+                next.Xt, r);
+    return;
+  }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (ts) {
@@ -735,9 +750,12 @@ hipError_t mlp_backward_step(const MlpGemmJob& back, const float* Z, __bf16* dZ,
 }
 hipError_t mlp_adam_pack(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
                          float eps, float c1, float c2, const MlpLayers& L, const TrainStep* ts,
-                         const float* part1, size_t zstride1, int ldp1, hipStream_t s) {
-  hipLaunchKernelGGL(k_adam_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps,
-                     c1, c2, L, ts, part1, zstride1, ldp1);
+                         const float* part1, size_t zstride1, int ldp1, const MlpNextInputs* next, hipStream_t s) {
+  if (next && (!ts || next->B < 1 || next->n_in < 1 || next->n_in > 16)) return hipErrorInvalidValue;
+  const int adam_blocks = (int)((n + 255) / 256);
+  const int scale_blocks = next ? (next->B + 255) / 256 : 0;
+  hipLaunchKernelGGL(k_adam_pack, dim3((unsigned)(adam_blocks + scale_blocks)), dim3(256), 0, s, w, m, v, g, n, lr,
+                     b1, b2, eps, c1, c2, L, ts, part1, zstride1, ldp1, next ? *next : MlpNextInputs{}, adam_blocks);
   return hipGetLastError();
 }
 hipError_t mlp_infer256(const float* x, int n, int n_in, const float* lohi, const __bf16* W1, const float* b1,
