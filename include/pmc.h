@@ -417,7 +417,7 @@ typedef struct pmc_train_opts {
  * float prices) in order, one Adam step per full batch (a trailing partial
  * batch is skipped); *mean_loss receives the mean squared error of the
  * scaled target over the pass.  o->batch must be a multiple of 64.  A step
- * (forward, loss, gradients, Adam with the BF16 repack of the weights: 9
+ * (forward, loss, gradients, Adam with the BF16 repack of the weights: 6
  * launches) is captured 16 times in a row as one HIP graph per batch size,
  * replayed for every 16 steps (the steps left over in a pass are launched
  * one by one); the batch position, learning rate and bias corrections are

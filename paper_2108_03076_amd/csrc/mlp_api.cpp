@@ -125,10 +125,27 @@ int ensure_batch(pmc_mlp* M, int B) {
 
 // Forward pass over B rows (n real) of raw inputs x (with ts: the step
 // record's batch); saves what backward needs when train is set.
-int forward(pmc_mlp* M, const float* x, int n, int B, bool train, const TrainStep* ts = nullptr) {
+int forward(pmc_mlp* M, const float* x, int n, int B, bool train, const TrainStep* ts = nullptr,
+            const float* y = nullptr) {
   hipStream_t s = stream_of(M);
   const int W = M->width;
   const float* w = M->master.as<float>();
+  if (train && W == 256) {
+    // one launch: the hidden layers (with Z, H, H^T) and the output layer
+    // with its loss gradient, from the scaled inputs
+    if (!ts)
+      MLP_TRY(M, mlp_scale_inputs(x, n, M->n_in, M->lohi.as<float>(), M->lohi.as<float>() + 32, B,
+                                  M->X.as<__bf16>(), M->Xt.as<__bf16>(), nullptr, s));
+    float* const Z[3] = {M->Z[0].as<float>(), M->Z[1].as<float>(), M->Z[2].as<float>()};
+    __bf16* const H[3] = {M->H[0].as<__bf16>(), M->H[1].as<__bf16>(), M->H[2].as<__bf16>()};
+    __bf16* const Ht[3] = {M->Ht[0].as<__bf16>(), M->Ht[1].as<__bf16>(), M->Ht[2].as<__bf16>()};
+    MLP_TRY(M, mlp_train_forward256(M->X.as<__bf16>(), Z, H, Ht, M->Wf[0].as<__bf16>(), w + M->ob[0],
+                                    M->Wf[1].as<__bf16>(), w + M->ob[1], M->Wf[2].as<__bf16>(), w + M->ob[2],
+                                    M->Wf[3].as<__bf16>(), w + M->ob[3], M->Y.as<float>(), y, n, B,
+                                    (float)(1.0 / M->y_scale), 2.0f / (float)n, M->dZ4.as<__bf16>(),
+                                    M->dZ4t.as<__bf16>(), ts, s));
+    return PMC_OK;
+  }
   // (a training step's inputs were scaled by the previous step's Adam
   // launch, or at the start of the pass)
   if (!ts)
@@ -165,7 +182,9 @@ int backward(pmc_mlp* M, const float* y, int n, int B, TrainStep* ts = nullptr) 
   float* g = M->grad.as<float>();
   const float inv_scale = (float)(1.0 / M->y_scale);
   // output layer: yhat, and its gradient dZ4 = 2 (yhat - y / y_scale) / n
-  MLP_TRY(M, mlp_gemm_out_train(B, W, M->H[2].as<__bf16>(), W, M->W[3].as<__bf16>(), W,
+  // (width 256: done by the forward launch)
+  if (W != 256)
+    MLP_TRY(M, mlp_gemm_out_train(B, W, M->H[2].as<__bf16>(), W, M->W[3].as<__bf16>(), W,
                                 M->master.as<float>() + M->ob[3], M->Y.as<float>(), y, n, inv_scale, 2.0f / (float)n,
                                 M->dZ4.as<__bf16>(), M->dZ4t.as<__bf16>(), ts, s));
   MlpLossJob loss;
@@ -373,7 +392,7 @@ extern "C" int pmc_mlp_loss_grad(pmc_mlp* m, const float* x, const float* y, int
   int rc = ensure_batch(m, B);
   if (rc != PMC_OK) return rc;
   MLP_TRY(m, hipMemsetAsync(m->loss_acc.p, 0, 8, s));
-  rc = forward(m, x, (int)n, B, true);
+  rc = forward(m, x, (int)n, B, true, nullptr, y);
   if (rc == PMC_OK) rc = backward(m, y, (int)n, B);
   if (rc != PMC_OK) return rc;
   double acc = 0;

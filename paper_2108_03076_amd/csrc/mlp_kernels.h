@@ -108,6 +108,17 @@ hipError_t mlp_backward_step(const MlpGemmJob& back, const float* Z, __bf16* dZ,
 hipError_t mlp_adam_pack(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
                          float eps, float c1, float c2, const MlpLayers& L, const TrainStep* ts,
                          const float* part1, size_t zstride1, int ldp1, const MlpNextInputs* next, hipStream_t s);
+// The forward pass of a training step for width 256 in one launch (B a
+// multiple of 64): from the scaled inputs X [B][16] the hidden layers'
+// Z (FP32 [B][256]), H (BF16 [B][256]) and Ht (BF16 [256][B]), yhat into
+// y [B] and the output gradient as mlp_gemm_out_train writes it, with the
+// fragment-ordered weights Wf (W1..W4) and FP32 biases; the same values bit
+// for bit as the per-layer kernels.
+hipError_t mlp_train_forward256(const __bf16* X, float* const Z[3], __bf16* const H[3], __bf16* const Ht[3],
+                                const __bf16* W1, const float* b1, const __bf16* W2, const float* b2,
+                                const __bf16* W3, const float* b3, const __bf16* W4, const float* b4, float* y,
+                                const float* t, int n, int B, float inv_scale, float grad_scale, __bf16* dZ,
+                                __bf16* dZt, const TrainStep* ts, hipStream_t s);
 // W [out_pad][in_pad], Wt [in_pad][out_pad] and the fragment-ordered Wf
 // (A-operand fragments of 32-row output tiles and 16-wide k steps, each
 // 64 lanes x 16 bytes, tile-major) from the FP32 master weights.

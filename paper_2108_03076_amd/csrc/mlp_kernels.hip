@@ -571,6 +571,27 @@ __device__ __forceinline__ void gelu_quad(const f32x16& acc, int q, __bf16* dst)
   *reinterpret_cast<bf16x4*>(dst + 8 * q) = v;
 }
 
+// A training forward also keeps each hidden layer's pre-activations Z
+// (FP32 [B][256]), activations H (BF16 [B][256]) and their transpose Ht
+// (BF16 [256][B]) for the backward pass; g0 is the block's first sample.
+struct LayerOut {
+  float* Z; __bf16* H; __bf16* Ht; int64_t g0; int B;
+};
+// The quad's values as gelu_quad stores them, into the training outputs
+// (sample `row` of the block, the tile's features f0 .. f0 + 3).
+__device__ __forceinline__ void keep_quad(const f32x16& acc, int q, const LayerOut& to, int row, int f0) {
+  const int64_t s = to.g0 + row;
+  const int f = f0 + 8 * q;
+  float4 z;
+  z.x = acc[4 * q + 0]; z.y = acc[4 * q + 1]; z.z = acc[4 * q + 2]; z.w = acc[4 * q + 3];
+  *reinterpret_cast<float4*>(to.Z + s * kInferW + f) = z;
+  bf16x4 h;
+  h[0] = to_bf16(gelu(z.x)); h[1] = to_bf16(gelu(z.y)); h[2] = to_bf16(gelu(z.z)); h[3] = to_bf16(gelu(z.w));
+  *reinterpret_cast<bf16x4*>(to.H + s * kInferW + f) = h;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) to.Ht[(int64_t)(f + i) * to.B + s] = h[i];
+}
+
 // One hidden layer (K = 16 KS inputs, 256 outputs) for the block's 64
 // samples: out = gelu(b + W in).  The products of sample tile 1 are
 // written interleaved with the GELU of tile 0 (one quad per four k steps),
@@ -578,9 +599,10 @@ __device__ __forceinline__ void gelu_quad(const f32x16& acc, int q, __bf16* dst)
 // the next layer's weights are loaded into the weight registers once this
 // layer's products are issued, half before and half after the GELU of
 // tile 1 (their latency hides behind the GELU and the barrier).
-template <int KS, int KSN, bool NEXT_OUT = false>
+template <int KS, int KSN, bool NEXT_OUT = false, bool TRAIN = false>
 __device__ __forceinline__ void hidden_layer(const __bf16* in, __bf16* out, bf16x8 (&wf)[16],
-                                             const float* __restrict__ bl, const __bf16* __restrict__ Wnext) {
+                                             const float* __restrict__ bl, const __bf16* __restrict__ Wnext,
+                                             const LayerOut& to = LayerOut{}) {
   const int lane = threadIdx.x & 63, r = lane & 31, kh = (lane >> 5) * 8, w = threadIdx.x >> 6;
   const int h4 = 4 * (lane >> 5);
   f32x16 acc[2];   // [sample tile]
@@ -602,10 +624,18 @@ __device__ __forceinline__ void hidden_layer(const __bf16* in, __bf16* out, bf16
 #pragma unroll
     for (int q = 0; q < 4; ++q) gelu_quad(acc[0], q, o0);
   }
+  if constexpr (TRAIN) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) keep_quad(acc[0], q, to, r, 32 * w + h4);
+  }
   load_weights<KSN, 0, KSN / 2, NEXT_OUT>(wf, Wnext);
   __bf16* o1 = out + (32 + r) * kInferLd + 32 * w + h4;
 #pragma unroll
   for (int q = 0; q < 4; ++q) gelu_quad(acc[1], q, o1);
+  if constexpr (TRAIN) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) keep_quad(acc[1], q, to, 32 + r, 32 * w + h4);
+  }
   load_weights<KSN, KSN / 2, KSN, NEXT_OUT>(wf, Wnext);
 }
 
@@ -654,6 +684,75 @@ __global__ __launch_bounds__(kInferThreads) __attribute__((amdgpu_waves_per_eu(4
       out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[k], b, out, 0, 0, 0);
     }
     if (lane < 32 && g0 + 32 * w + r < n) y[g0 + 32 * w + r] = out[0] * y_scale;
+  }
+}
+
+// The forward pass of a training step for width 256 in one launch, as
+// k_mlp_infer256 computes it (the same values bit for bit as the per-layer
+// kernels): the block's 64 rows of the scaled inputs X [B][16] are read
+// into LDS, each hidden layer also keeps Z, H and Ht (LayerOut), and the
+// output layer writes yhat into y and the output gradient d = grad_scale
+// (yhat - t inv_scale) (0 for rows >= n; t the targets or the step
+// record's batch) as column 0 of dZ [B][32] and row 0 of dZt [32][B],
+// every other element of both 0.
+struct TrainFwd {
+  const __bf16* X; float* Z[3]; __bf16* H[3]; __bf16* Ht[3]; float* y; const float* t; const TrainStep* ts;
+  int n, B; float inv_scale, grad_scale; __bf16* dZ; __bf16* dZt;
+};
+// (A training batch of B samples is B / 64 blocks, far fewer than the
+// CUs at the usual batch sizes: the kernel takes the registers it needs
+// rather than the four waves per SIMD of inference, which spilled.)
+__global__ __launch_bounds__(kInferThreads) __attribute__((amdgpu_waves_per_eu(2, 4))) void k_mlp_train_fwd256(
+    TrainFwd a, const __bf16* __restrict__ W1, const float* __restrict__ b1, const __bf16* __restrict__ W2,
+    const float* __restrict__ b2, const __bf16* __restrict__ W3, const float* __restrict__ b3,
+    const __bf16* __restrict__ W4, const float* __restrict__ b4) {
+  __shared__ __bf16 act[2][kInferRows * kInferLd];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 31, kh = (lane >> 5) * 8;
+  const int64_t g0 = (int64_t)blockIdx.x * kInferRows;
+  bf16x8 wf[16];
+  load_weights<1>(wf, W1);
+  if (threadIdx.x < 2 * kInferRows) {   // row t/2, columns 8 (t%2) ..
+    const int row = threadIdx.x >> 1, c = 8 * (threadIdx.x & 1);
+    *reinterpret_cast<bf16x8*>(&act[0][row * kInferLd + c]) =
+        *reinterpret_cast<const bf16x8*>(a.X + (g0 + row) * 16 + c);
+  }
+  __syncthreads();
+  hidden_layer<1, 16, false, true>(act[0], act[1], wf, b1, W2, LayerOut{a.Z[0], a.H[0], a.Ht[0], g0, a.B});
+  __syncthreads();
+  hidden_layer<16, 16, false, true>(act[1], act[0], wf, b2, W3, LayerOut{a.Z[1], a.H[1], a.Ht[1], g0, a.B});
+  __syncthreads();
+  hidden_layer<16, 16, true, true>(act[0], act[1], wf, b3, W4, LayerOut{a.Z[2], a.H[2], a.Ht[2], g0, a.B});
+  __syncthreads();
+  if (w < 2) {   // waves 0 and 1: samples 32w .. 32w + 31; feature 0 is element 0 of lanes 0..31
+    f32x16 out;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) out[e] = 0.0f;
+    if (lane < 32) out[0] = b4[0];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&act[1][(32 * w + r) * kInferLd + 16 * k + kh]);
+      out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[k], b, out, 0, 0, 0);
+    }
+    if (lane < 32) {
+      const int64_t row = g0 + 32 * w + r;
+      const float v = out[0];
+      a.y[row] = v;
+      float d = 0.0f;
+      if (row < a.n) {
+        const float* tt = a.ts ? a.ts->y + a.ts->step * (int64_t)a.B : a.t;
+        const float e = v - tt[row] * a.inv_scale;
+        d = a.grad_scale * e;
+      }
+      const __bf16 db = to_bf16(d);
+      bf16x8 first, zero;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) { first[j] = to_bf16(0.0f); zero[j] = to_bf16(0.0f); }
+      first[0] = db;
+      bf16x8* pz = reinterpret_cast<bf16x8*>(a.dZ + row * 32);
+      pz[0] = first; pz[1] = zero; pz[2] = zero; pz[3] = zero;
+#pragma unroll
+      for (int j = 0; j < 32; ++j) a.dZt[(int64_t)j * a.B + row] = j == 0 ? db : to_bf16(0.0f);
+    }
   }
 }
 
@@ -764,6 +863,18 @@ hipError_t mlp_infer256(const float* x, int n, int n_in, const float* lohi, cons
   if (n < 1 || n_in < 1 || n_in > 16) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_mlp_infer256, dim3((n + kInferRows - 1) / kInferRows), dim3(kInferThreads), 0, s, x, n, n_in,
                      lohi, W1, b1, W2, b2, W3, b3, W4, b4, y_scale, y);
+  return hipGetLastError();
+}
+hipError_t mlp_train_forward256(const __bf16* X, float* const Z[3], __bf16* const H[3], __bf16* const Ht[3],
+                                const __bf16* W1, const float* b1, const __bf16* W2, const float* b2,
+                                const __bf16* W3, const float* b3, const __bf16* W4, const float* b4, float* y,
+                                const float* t, int n, int B, float inv_scale, float grad_scale, __bf16* dZ,
+                                __bf16* dZt, const TrainStep* ts, hipStream_t s) {
+  if (B < 64 || B % 64 || n < 0 || n > B || (!t && !ts)) return hipErrorInvalidValue;
+  TrainFwd a{X, {Z[0], Z[1], Z[2]}, {H[0], H[1], H[2]}, {Ht[0], Ht[1], Ht[2]}, y, t, ts, n, B, inv_scale, grad_scale,
+             dZ, dZt};
+  hipLaunchKernelGGL(k_mlp_train_fwd256, dim3(B / kInferRows), dim3(kInferThreads), 0, s, a, W1, b1, W2, b2, W3, b3,
+                     W4, b4);
   return hipGetLastError();
 }
 hipError_t mlp_pack(const float* master, int out, int in, int out_pad, int in_pad, __bf16* W, __bf16* Wt,
