@@ -109,7 +109,7 @@ hipError_t mlp_adam_pack(float* w, float* m, float* v, const float* g, int64_t n
                          float eps, float c1, float c2, const MlpLayers& L, const TrainStep* ts,
                          const float* part1, size_t zstride1, int ldp1, const MlpNextInputs* next, hipStream_t s);
 // The forward pass of a training step for width 256 in one launch (B a
-// multiple of 64): from the scaled inputs X [B][16] the hidden layers'
+// multiple of 32): from the scaled inputs X [B][16] the hidden layers'
 // Z (FP32 [B][256]), H (BF16 [B][256]) and Ht (BF16 [256][B]), yhat into
 // y [B] and the output gradient as mlp_gemm_out_train writes it, with the
 // fragment-ordered weights Wf (W1..W4) and FP32 biases; the same values bit

@@ -599,7 +599,7 @@ __device__ __forceinline__ void keep_quad(const f32x16& acc, int q, const LayerO
 // the next layer's weights are loaded into the weight registers once this
 // layer's products are issued, half before and half after the GELU of
 // tile 1 (their latency hides behind the GELU and the barrier).
-template <int KS, int KSN, bool NEXT_OUT = false, bool TRAIN = false>
+template <int KS, int KSN, bool NEXT_OUT = false, bool TRAIN = false, int ST = 2>
 __device__ __forceinline__ void hidden_layer(const __bf16* in, __bf16* out, bf16x8 (&wf)[16],
                                              const float* __restrict__ bl, const __bf16* __restrict__ Wnext,
                                              const LayerOut& to = LayerOut{}) {
@@ -607,7 +607,24 @@ __device__ __forceinline__ void hidden_layer(const __bf16* in, __bf16* out, bf16
   const int h4 = 4 * (lane >> 5);
   f32x16 acc[2];   // [sample tile]
 #pragma unroll
-  for (int st = 0; st < 2; ++st) bias_init(acc[st], bl + 32 * w);
+  for (int st = 0; st < ST; ++st) bias_init(acc[st], bl + 32 * w);
+  if constexpr (ST == 1) {   // one sample tile: products, then GELU
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(in + r * kInferLd + 16 * k + kh);
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[k], b, acc[0], 0, 0, 0);
+    }
+    load_weights<KSN, 0, KSN / 2, NEXT_OUT>(wf, Wnext);
+    __bf16* o0 = out + r * kInferLd + 32 * w + h4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) gelu_quad(acc[0], q, o0);
+    if constexpr (TRAIN) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) keep_quad(acc[0], q, to, r, 32 * w + h4);
+    }
+    load_weights<KSN, KSN / 2, KSN, NEXT_OUT>(wf, Wnext);
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
     const bf16x8 b = *reinterpret_cast<const bf16x8*>(in + r * kInferLd + 16 * k + kh);
@@ -702,28 +719,29 @@ struct TrainFwd {
 // (A training batch of B samples is B / 64 blocks, far fewer than the
 // CUs at the usual batch sizes: the kernel takes the registers it needs
 // rather than the four waves per SIMD of inference, which spilled.)
+constexpr int kTrainRows = 32;   // samples per block of the training forward (one sample tile)
 __global__ __launch_bounds__(kInferThreads) __attribute__((amdgpu_waves_per_eu(2, 4))) void k_mlp_train_fwd256(
     TrainFwd a, const __bf16* __restrict__ W1, const float* __restrict__ b1, const __bf16* __restrict__ W2,
     const float* __restrict__ b2, const __bf16* __restrict__ W3, const float* __restrict__ b3,
     const __bf16* __restrict__ W4, const float* __restrict__ b4) {
-  __shared__ __bf16 act[2][kInferRows * kInferLd];
+  __shared__ __bf16 act[2][kTrainRows * kInferLd];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 31, kh = (lane >> 5) * 8;
-  const int64_t g0 = (int64_t)blockIdx.x * kInferRows;
+  const int64_t g0 = (int64_t)blockIdx.x * kTrainRows;
   bf16x8 wf[16];
   load_weights<1>(wf, W1);
-  if (threadIdx.x < 2 * kInferRows) {   // row t/2, columns 8 (t%2) ..
+  if (threadIdx.x < 2 * kTrainRows) {   // row t/2, columns 8 (t%2) ..
     const int row = threadIdx.x >> 1, c = 8 * (threadIdx.x & 1);
     *reinterpret_cast<bf16x8*>(&act[0][row * kInferLd + c]) =
         *reinterpret_cast<const bf16x8*>(a.X + (g0 + row) * 16 + c);
   }
   __syncthreads();
-  hidden_layer<1, 16, false, true>(act[0], act[1], wf, b1, W2, LayerOut{a.Z[0], a.H[0], a.Ht[0], g0, a.B});
+  hidden_layer<1, 16, false, true, 1>(act[0], act[1], wf, b1, W2, LayerOut{a.Z[0], a.H[0], a.Ht[0], g0, a.B});
   __syncthreads();
-  hidden_layer<16, 16, false, true>(act[1], act[0], wf, b2, W3, LayerOut{a.Z[1], a.H[1], a.Ht[1], g0, a.B});
+  hidden_layer<16, 16, false, true, 1>(act[1], act[0], wf, b2, W3, LayerOut{a.Z[1], a.H[1], a.Ht[1], g0, a.B});
   __syncthreads();
-  hidden_layer<16, 16, true, true>(act[0], act[1], wf, b3, W4, LayerOut{a.Z[2], a.H[2], a.Ht[2], g0, a.B});
+  hidden_layer<16, 16, true, true, 1>(act[0], act[1], wf, b3, W4, LayerOut{a.Z[2], a.H[2], a.Ht[2], g0, a.B});
   __syncthreads();
-  if (w < 2) {   // waves 0 and 1: samples 32w .. 32w + 31; feature 0 is element 0 of lanes 0..31
+  if (w < 1) {   // wave 0: the block's 32 samples; feature 0 is element 0 of lanes 0..31
     f32x16 out;
 #pragma unroll
     for (int e = 0; e < 16; ++e) out[e] = 0.0f;
@@ -870,10 +888,10 @@ hipError_t mlp_train_forward256(const __bf16* X, float* const Z[3], __bf16* cons
                                 const __bf16* W3, const float* b3, const __bf16* W4, const float* b4, float* y,
                                 const float* t, int n, int B, float inv_scale, float grad_scale, __bf16* dZ,
                                 __bf16* dZt, const TrainStep* ts, hipStream_t s) {
-  if (B < 64 || B % 64 || n < 0 || n > B || (!t && !ts)) return hipErrorInvalidValue;
+  if (B < kTrainRows || B % kTrainRows || n < 0 || n > B || (!t && !ts)) return hipErrorInvalidValue;
   TrainFwd a{X, {Z[0], Z[1], Z[2]}, {H[0], H[1], H[2]}, {Ht[0], Ht[1], Ht[2]}, y, t, ts, n, B, inv_scale, grad_scale,
              dZ, dZt};
-  hipLaunchKernelGGL(k_mlp_train_fwd256, dim3(B / kInferRows), dim3(kInferThreads), 0, s, a, W1, b1, W2, b2, W3, b3,
+  hipLaunchKernelGGL(k_mlp_train_fwd256, dim3(B / kTrainRows), dim3(kInferThreads), 0, s, a, W1, b1, W2, b2, W3, b3,
                      W4, b4);
   return hipGetLastError();
 }
